@@ -1,0 +1,156 @@
+/* lamino.h -- C ABI of the MI355X laminography library.
+ *
+ * The library evaluates the laminographic projection L (eq:fwd), its
+ * adjoint L* (eq:adj) and the filtered backprojection W L* (eq:recon) by
+ * the Fourier route of the paper (eq:fftfwd, eq:fftadj): a 2D FFT per
+ * projection, a Gaussian unequally-spaced FFT onto the tilted frequency
+ * grid of eq:uneqspace, split as in eq:fftfwdsplit into per-slab 2D
+ * transforms and a transform along x3.
+ *
+ * Conventions (all sizes in elements, all arrays C-order, row-major):
+ *   volume  vol[nz][n][n], float32, x1 = ix - n/2 fastest, then
+ *           x2 = iy - n/2, x3 = iz - nz/2 (integer division), voxel = 1;
+ *   data    d[n_theta][h][w] in opts.data_dtype, detector column
+ *           u = c - w/2 fastest, row v = r - h/2, pixel = 1;
+ *   angles  theta_j (radians, any values; default 2 pi j / n_theta);
+ *   tilt    phi in radians, 0 == tomography, |phi| < pi/2.
+ * The detector is zero-padded to h_p x w_p (powers of two >= pad * (h, w));
+ * frequencies are m / w_p and l / h_p without the Nyquist bins.  Under
+ * these conventions lamino_fwd and lamino_adj are an exact adjoint pair
+ * (up to rounding and the USFFT kernel truncation, which both share), and
+ * lamino_fbp applies W(m) = (pi / n_theta) cos(phi) |m / w_p| window(m / w_p)
+ * before backprojection (the Jacobian of eq:uneqspace and the double cover
+ * of xi by theta in [0, 2 pi)).
+ *
+ * Memory ownership: the library never allocates device memory.  The caller
+ * allocates the table and workspace buffers whose sizes lamino_plan_sizes
+ * reports, binds them once with lamino_plan_bind, and passes input and
+ * output device buffers to each call.  A plan with its workspace serves
+ * one call at a time; concurrent calls need separate plans/workspaces.
+ *
+ * Streams: every call is asynchronous on the given HIP stream
+ * (hipStream_t passed as void*; NULL = the default stream).  Results are
+ * ready when the stream is synchronised.
+ *
+ * Errors: functions return LAMINO_OK (0) or a negative code; no call
+ * throws.  lamino_last_error() gives a thread-local message for the last
+ * failure on the calling thread.
+ */
+#ifndef LAMINO_H
+#define LAMINO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lamino_plan_s lamino_plan_t;
+
+typedef enum { LAMINO_F32 = 0, LAMINO_F16 = 1, LAMINO_BF16 = 2 } lamino_dtype;
+
+/* Window of the FBP filter (the paper names ramp, Shepp-Logan, Parzen). */
+typedef enum { LAMINO_RAMP = 0, LAMINO_SHEPP_LOGAN = 1, LAMINO_PARZEN = 2 } lamino_filter;
+
+enum {
+  LAMINO_OK = 0,
+  LAMINO_E_INVALID = -1,     /* bad argument: sizes, tilt, NULL pointer */
+  LAMINO_E_UNSUPPORTED = -2, /* size outside what the kernels support   */
+  LAMINO_E_BUDGET = -3,      /* workspace exceeds opts.hbm_budget        */
+  LAMINO_E_HIP = -4,         /* HIP runtime or launch error              */
+  LAMINO_E_UNBOUND = -5      /* plan used before lamino_plan_bind        */
+};
+
+/* Scan geometry (eq:fwd).  theta is a host array of n_theta radians or
+ * NULL for 2 pi j / n_theta; it is copied by lamino_plan. */
+typedef struct {
+  int nz, n;       /* volume nz x n x n                         */
+  int n_theta;     /* number of projections                     */
+  int h, w;        /* detector rows x columns                   */
+  double tilt;     /* phi (radians)                             */
+  const double* theta;
+} lamino_geom;
+
+/* Options; zero-initialise and then call lamino_opts_default. */
+typedef struct {
+  int data_dtype;     /* lamino_dtype of d                                    */
+  int storage_dtype;  /* lamino_dtype of the stored spectra and slab planes;
+                         arithmetic is always float32                         */
+  int filter;         /* lamino_filter used by lamino_fbp                      */
+  double pad_u, pad_v;/* detector padding factors (>= 1), default 2           */
+  int kernel_m;       /* Gaussian half-width M in grid cells (1..8); 0 picks
+                         5 for F32 storage and 3 for F16/BF16 storage          */
+  int z_chunk;        /* x3-transform output slices per launch; 0 = nz         */
+  int slab_chunk;     /* frequency slabs gridded per pass; 0 = automatic       */
+  int theta_chunk;    /* projections per detector-FFT pass; 0 = automatic      */
+  size_t hbm_budget;  /* max workspace bytes; 0 = no limit                    */
+} lamino_opts;
+
+/* Derived sizes of a plan (read-only description). */
+typedef struct {
+  int h_p, w_p;       /* padded detector                                      */
+  int n_slab;         /* stored frequency slabs l = 0 .. h_p/2 - 1             */
+  int grid;           /* per-slab USFFT grid N_g (power of two >= 2 n)        */
+  int kernel_m;       /* Gaussian half-width M                                */
+  double beta;        /* Gaussian exponent: phi(t) = exp(-beta t^2), t in cells*/
+  int z_chunk, slab_chunk, theta_chunk;
+  size_t table_bytes, work_bytes;
+  size_t off_spectra, bytes_spectra; /* D[l][theta][k] in the workspace       */
+  size_t off_slabs, bytes_slabs;     /* g[l][y][x] in the workspace           */
+} lamino_info;
+
+/* Fill *opts with defaults (F32 data and storage, Shepp-Logan, pad 2). */
+void lamino_opts_default(lamino_opts* opts);
+
+/* Create a plan for geometry *geom (host-only: no HIP call).  Computes the
+ * per-angle trigonometry, the x3 phase table, the filter, the USFFT psi
+ * correction and FFT twiddles in double precision and keeps them on the
+ * host until bind.  opts may be NULL (defaults).  On success *out owns a
+ * new plan.  Errors: E_INVALID (non-positive sizes, |tilt| >= pi/2,
+ * non-finite values, NULL out), E_UNSUPPORTED (a padded size above 4096 or
+ * a grid the FFT kernels do not cover), E_BUDGET (workspace > hbm_budget
+ * even at the smallest chunks). */
+int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t** out);
+
+/* Bytes of the device table buffer and the device workspace the caller
+ * must provide to lamino_plan_bind (each 256-byte aligned).  Host-only. */
+int lamino_plan_sizes(const lamino_plan_t* plan, size_t* table_bytes, size_t* work_bytes);
+
+/* Derived sizes and workspace layout.  Host-only. */
+int lamino_plan_info(const lamino_plan_t* plan, lamino_info* info);
+
+/* Attach caller-owned device buffers (d_tables: table_bytes, d_work:
+ * work_bytes, both 256-byte aligned) and upload the tables on `stream`.
+ * The buffers must outlive every later call with this plan.  Rebinding is
+ * allowed.  Errors: E_INVALID (NULL/misaligned buffers), E_HIP. */
+int lamino_plan_bind(lamino_plan_t* plan, void* d_tables, void* d_work, void* stream);
+
+/* Filtered backprojection (eq:recon via eq:fftadj): vol = L*(W d).
+ * d_data: device d[n_theta][h][w] in data_dtype (read only);
+ * d_vol: device float vol[nz][n][n] (written).  Errors: E_INVALID,
+ * E_UNBOUND, E_HIP. */
+int lamino_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
+/* Forward projection (eq:fwd via eq:fftfwd): d = L vol.
+ * d_vol: device float vol[nz][n][n] (read only); d_data: device
+ * d[n_theta][h][w] in data_dtype (written).  Errors as lamino_fbp. */
+int lamino_fwd(const lamino_plan_t* plan, const float* d_vol, void* d_data, void* stream);
+
+/* Adjoint (eq:adj via eq:fftadj): vol = L* d, the exact transpose of
+ * lamino_fwd.  Arguments as lamino_fbp. */
+int lamino_adj(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
+/* Free the host plan (device buffers stay with the caller). NULL is ok. */
+int lamino_plan_destroy(lamino_plan_t* plan);
+
+/* Static description of a status code. */
+const char* lamino_strerror(int status);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* lamino_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAMINO_H */

@@ -97,6 +97,27 @@ def data_spectra(d, geom):
     return np.einsum("lv,tvu,um->tlm", Fv, d, Fu, optimize=True) / (geom.h_p * geom.w_p)
 
 
+def data_spectra_fft(d, geom, half=False):
+    """The same G computed with numpy's FFT of the zero-padded data.
+
+    half=True keeps l >= 0 only (for large inputs); rows are then
+    l = 0 .. h_p/2 - 1."""
+    d = np.asarray(d, dtype=np.float64)
+    T = geom.n_theta
+    ms = freqs(geom.w_p)
+    ls = np.arange(geom.h_p // 2) if half else freqs(geom.h_p)
+    out = np.empty((T, len(ls), len(ms)), dtype=np.complex128)
+    rows = centred(geom.h) % geom.h_p
+    cols = centred(geom.w) % geom.w_p
+    for t0 in range(0, T, 16):
+        t1 = min(T, t0 + 16)
+        pad = np.zeros((t1 - t0, geom.h_p, geom.w_p))
+        pad[:, rows[:, None], cols[None, :]] = d[t0:t1]
+        F = np.fft.fft2(pad) / (geom.h_p * geom.w_p)
+        out[t0:t1] = F[:, (ls % geom.h_p)[:, None], (ms % geom.w_p)[None, :]]
+    return out
+
+
 def filter_spectra(G, geom, kind):
     """Multiply by the FBP weight W(m) of eq:recon (see `filters`)."""
     W = filters.fbp_weight(freqs(geom.w_p), geom.w_p, geom.n_theta, geom.phi, kind)

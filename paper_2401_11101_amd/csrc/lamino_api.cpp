@@ -1,0 +1,389 @@
+// Host side of the C ABI: validation, double-precision tables, workspace
+// layout, binding and the three operator entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lamino_common.h"
+#include "lamino_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(LAMINO_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int pow2_at_least(double x) {
+  long p = 1;
+  while ((double)p < x && p < (1L << 30)) p *= 2;
+  return (int)p;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Transfer-function windows of the FBP filter, k in cycles per pixel.
+double window(double k, int kind) {
+  k = std::fabs(k);
+  if (kind == LAMINO_RAMP) return 1.0;
+  if (kind == LAMINO_SHEPP_LOGAN) return k == 0.0 ? 1.0 : std::sin(M_PI * k) / (M_PI * k);
+  const double t = 2.0 * k;  // Parzen on [-1/2, 1/2]
+  if (t <= 0.5) return 1.0 - 6.0 * t * t * (1.0 - t);
+  if (t <= 1.0) return 2.0 * (1.0 - t) * (1.0 - t) * (1.0 - t);
+  return 0.0;
+}
+
+constexpr size_t kChunkTarget = 128u << 20;  // bytes per chunked intermediate
+
+// Bytes of one slab's padded spreading tiles (tile + 2M - 1 per edge).
+size_t padded_slab_bytes(const lamino_plan_s* p) {
+  const size_t t = lam::gridding_tile(p->grid);
+  const size_t P = t + 2 * p->M - 1;
+  const size_t nt = p->grid / t;
+  return nt * nt * P * P * 8;
+}
+
+void layout_work(lamino_plan_s* p) {
+  const size_t sb = lam::storage_bytes(p->opts.storage_dtype);
+  p->bytes_w1 = (size_t)p->theta_chunk * p->n_slab * p->w * 8;
+  p->bytes_D = (size_t)p->n_slab * p->n_theta * p->w_p * sb;
+  p->bytes_G = (size_t)p->slab_chunk * p->grid * p->grid * 8;
+  p->bytes_Gp = (size_t)p->slab_chunk * padded_slab_bytes(p);
+  p->bytes_g = (size_t)p->n_slab * p->n * p->n * sb;
+  size_t off = 0;
+  p->off_w1 = off;
+  off += align256(p->bytes_w1);
+  p->off_D = off;
+  off += align256(p->bytes_D);
+  p->off_G = off;
+  off += align256(p->bytes_G);
+  p->off_Gp = off;
+  off += align256(p->bytes_Gp);
+  p->off_g = off;
+  off += align256(p->bytes_g);
+  p->work_bytes = off;
+}
+
+void build_tables(lamino_plan_s* p) {
+  const double phi = p->tilt;
+  const double cphi = std::cos(phi);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const int twmax = std::max(std::max(p->h_p, p->w_p), p->grid);
+  p->log2_twmax = lam::ilog2(twmax);
+  p->off_trig = take((size_t)p->n_theta * 8);
+  p->off_filt_fbp = take((size_t)p->w_p * 4);
+  p->off_filt_adj = take((size_t)p->w_p * 4);
+  p->off_deapod = take((size_t)p->n * 4);
+  p->off_e_adj = take((size_t)p->nz * p->n_slab * 8);
+  p->off_e_fwd = take((size_t)p->n_slab * p->nz * 8);
+  p->off_tw = take((size_t)twmax * 8);
+  p->table_bytes = off;
+  p->host_tables.assign(off, 0);
+  unsigned char* base = p->host_tables.data();
+
+  float* trig = reinterpret_cast<float*>(base + p->off_trig);
+  for (int j = 0; j < p->n_theta; ++j) {
+    trig[2 * j] = (float)std::cos(p->theta[j]);
+    trig[2 * j + 1] = (float)std::sin(p->theta[j]);
+  }
+  // W(m) / (h_p w_p) for FBP and 1 / (h_p w_p) for L*, indexed by k = m mod w_p;
+  // the Nyquist bin k = w_p / 2 is not part of the sums.
+  float* ffbp = reinterpret_cast<float*>(base + p->off_filt_fbp);
+  float* fadj = reinterpret_cast<float*>(base + p->off_filt_adj);
+  const double norm = 1.0 / ((double)p->h_p * p->w_p);
+  for (int k = 0; k < p->w_p; ++k) {
+    const int m = k < p->w_p / 2 ? k : k - p->w_p;
+    const double km = (double)m / p->w_p;
+    const bool nyq = (k == p->w_p / 2);
+    ffbp[k] = nyq ? 0.f
+                  : (float)(M_PI / p->n_theta * cphi * std::fabs(km) * window(km, p->opts.filter) * norm);
+    fadj[k] = nyq ? 0.f : (float)norm;
+  }
+  // psi correction of the Gaussian USFFT per axis
+  float* deap = reinterpret_cast<float*>(base + p->off_deapod);
+  for (int i = 0; i < p->n; ++i) {
+    const double x = i - p->n / 2;
+    deap[i] = (float)(std::sqrt(p->beta / M_PI) *
+                      std::exp(M_PI * M_PI * x * x / (p->beta * (double)p->grid * p->grid)));
+  }
+  // x3 phases: xi3 = l cos(phi) / h_p (eq:uneqspace)
+  float* ea = reinterpret_cast<float*>(base + p->off_e_adj);
+  float* ef = reinterpret_cast<float*>(base + p->off_e_fwd);
+  for (int z = 0; z < p->nz; ++z) {
+    const double x3 = z - p->nz / 2;
+    for (int l = 0; l < p->n_slab; ++l) {
+      const double a = 2.0 * M_PI * x3 * l * cphi / p->h_p;
+      const double wl = l == 0 ? 1.0 : 2.0;
+      ea[2 * ((size_t)z * p->n_slab + l)] = (float)(wl * std::cos(a));
+      ea[2 * ((size_t)z * p->n_slab + l) + 1] = (float)(wl * std::sin(a));
+      ef[2 * ((size_t)l * p->nz + z)] = (float)std::cos(a);
+      ef[2 * ((size_t)l * p->nz + z) + 1] = (float)(-std::sin(a));
+    }
+  }
+  float* tw = reinterpret_cast<float*>(base + p->off_tw);
+  for (int t = 0; t < twmax; ++t) {
+    const double a = -2.0 * M_PI * t / twmax;
+    tw[2 * t] = (float)std::cos(a);
+    tw[2 * t + 1] = (float)std::sin(a);
+  }
+}
+
+}  // namespace
+
+namespace lam {
+
+size_t storage_bytes(int dtype) { return dtype == LAMINO_F32 ? 8 : 4; }
+size_t data_bytes(int dtype) { return dtype == LAMINO_F32 ? 4 : 2; }
+
+KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
+  KParams k;
+  k.nz = p->nz;
+  k.n = p->n;
+  k.n_theta = p->n_theta;
+  k.h = p->h;
+  k.w = p->w;
+  k.h_p = p->h_p;
+  k.w_p = p->w_p;
+  k.n_slab = p->n_slab;
+  k.grid = p->grid;
+  k.M = p->M;
+  k.log2_hp = ilog2(p->h_p);
+  k.log2_wp = ilog2(p->w_p);
+  k.log2_grid = ilog2(p->grid);
+  k.log2_twmax = p->log2_twmax;
+  k.beta = (float)p->beta;
+  k.ncw = (float)((double)p->grid / p->w_p);
+  k.gs = (float)((double)p->grid * std::sin(p->tilt) / p->h_p);
+  k.data_dtype = p->opts.data_dtype;
+  k.storage_dtype = p->opts.storage_dtype;
+  const char* t = static_cast<const char*>(p->d_tables);
+  k.trig = reinterpret_cast<const float2*>(t + p->off_trig);
+  k.filt = reinterpret_cast<const float*>(t + (fbp_filter ? p->off_filt_fbp : p->off_filt_adj));
+  k.deapod = reinterpret_cast<const float*>(t + p->off_deapod);
+  k.e_adj = reinterpret_cast<const float2*>(t + p->off_e_adj);
+  k.e_fwd = reinterpret_cast<const float2*>(t + p->off_e_fwd);
+  k.tw = reinterpret_cast<const float2*>(t + p->off_tw);
+  return k;
+}
+
+}  // namespace lam
+
+extern "C" {
+
+void lamino_opts_default(lamino_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->data_dtype = LAMINO_F32;
+  o->storage_dtype = LAMINO_F32;
+  o->filter = LAMINO_SHEPP_LOGAN;
+  o->pad_u = 2.0;
+  o->pad_v = 2.0;
+}
+
+int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t** out) {
+  g_last_error.clear();
+  if (!geom || !out) return fail(LAMINO_E_INVALID, "lamino_plan: NULL geometry or output");
+  *out = nullptr;
+  lamino_opts o;
+  lamino_opts_default(&o);
+  if (opts) o = *opts;
+  if (geom->nz < 1 || geom->n < 1 || geom->n_theta < 1 || geom->h < 1 || geom->w < 1)
+    return fail(LAMINO_E_INVALID, "lamino_plan: sizes must be positive (nz=%d n=%d n_theta=%d h=%d w=%d)",
+                geom->nz, geom->n, geom->n_theta, geom->h, geom->w);
+  if (geom->n_theta > 65535)
+    return fail(LAMINO_E_UNSUPPORTED, "lamino_plan: n_theta=%d above 65535", geom->n_theta);
+  if (!std::isfinite(geom->tilt) || std::fabs(geom->tilt) >= M_PI / 2)
+    return fail(LAMINO_E_INVALID, "lamino_plan: tilt must be finite with |tilt| < pi/2");
+  if (o.data_dtype < 0 || o.data_dtype > 2 || o.storage_dtype < 0 || o.storage_dtype > 2)
+    return fail(LAMINO_E_INVALID, "lamino_plan: unknown dtype");
+  if (o.filter < 0 || o.filter > 2) return fail(LAMINO_E_INVALID, "lamino_plan: unknown filter");
+  if (o.pad_u == 0.0) o.pad_u = 2.0;
+  if (o.pad_v == 0.0) o.pad_v = 2.0;
+  if (!(o.pad_u >= 1.0) || !(o.pad_v >= 1.0) || !std::isfinite(o.pad_u) || !std::isfinite(o.pad_v))
+    return fail(LAMINO_E_INVALID, "lamino_plan: padding factors must be >= 1");
+  if (o.kernel_m != 0 && (o.kernel_m < 2 || o.kernel_m > 8))
+    return fail(LAMINO_E_INVALID, "lamino_plan: kernel_m must be 0 or 2..8");
+  if (o.z_chunk < 0 || o.slab_chunk < 0 || o.theta_chunk < 0)
+    return fail(LAMINO_E_INVALID, "lamino_plan: chunk sizes must be >= 0");
+
+  lamino_plan_s* p = new (std::nothrow) lamino_plan_s();
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan: out of host memory");
+  p->nz = geom->nz;
+  p->n = geom->n;
+  p->n_theta = geom->n_theta;
+  p->h = geom->h;
+  p->w = geom->w;
+  p->tilt = geom->tilt;
+  p->opts = o;
+  p->theta.resize(p->n_theta);
+  for (int j = 0; j < p->n_theta; ++j) {
+    p->theta[j] = geom->theta ? geom->theta[j] : 2.0 * M_PI * j / p->n_theta;
+    if (!std::isfinite(p->theta[j])) {
+      delete p;
+      return fail(LAMINO_E_INVALID, "lamino_plan: theta[%d] is not finite", j);
+    }
+  }
+  p->w_p = pow2_at_least(std::ceil(o.pad_u * p->w));
+  p->h_p = pow2_at_least(std::ceil(o.pad_v * p->h));
+  p->grid = std::max(16, pow2_at_least(2.0 * p->n));
+  if (p->w_p < 2 || p->h_p < 2 || p->w_p > 4096 || p->h_p > 4096 || p->grid > 4096) {
+    const int wp = p->w_p, hp = p->h_p, gr = p->grid;
+    delete p;
+    return fail(LAMINO_E_UNSUPPORTED,
+                "lamino_plan: FFT sizes w_p=%d h_p=%d grid=%d outside [2, 4096]", wp, hp, gr);
+  }
+  p->n_slab = p->h_p / 2;
+  p->M = o.kernel_m ? o.kernel_m : (o.storage_dtype == LAMINO_F32 ? 5 : 3);
+  {
+    // Gaussian width of Greengard & Lee (2004) for oversampling R = grid / n,
+    // expressed in grid cells: phi(t) = exp(-beta t^2).
+    const double R = (double)p->grid / p->n;
+    p->beta = M_PI * (R - 0.5) / (R * p->M);
+  }
+  p->tile = 0;
+  p->z_chunk = o.z_chunk ? std::min(o.z_chunk, p->nz) : p->nz;
+  const size_t slab_bytes = (size_t)p->grid * p->grid * 8 + padded_slab_bytes(p);
+  const size_t w1_bytes = (size_t)p->n_slab * p->w * 8;
+  p->slab_chunk = o.slab_chunk ? std::min(o.slab_chunk, p->n_slab)
+                               : (int)std::max<size_t>(1, std::min<size_t>(p->n_slab, kChunkTarget / slab_bytes));
+  p->theta_chunk = o.theta_chunk ? std::min(o.theta_chunk, p->n_theta)
+                                 : (int)std::max<size_t>(1, std::min<size_t>(p->n_theta, kChunkTarget / w1_bytes));
+  layout_work(p);
+  if (o.hbm_budget) {
+    // shrink the chunked intermediates until the workspace fits
+    while (p->work_bytes > o.hbm_budget && (p->slab_chunk > 1 || p->theta_chunk > 1)) {
+      if (p->bytes_G + p->bytes_Gp >= p->bytes_w1 && p->slab_chunk > 1) p->slab_chunk = (p->slab_chunk + 1) / 2;
+      else if (p->theta_chunk > 1) p->theta_chunk = (p->theta_chunk + 1) / 2;
+      else p->slab_chunk = (p->slab_chunk + 1) / 2;
+      layout_work(p);
+    }
+    if (p->work_bytes > o.hbm_budget) {
+      const size_t need = p->work_bytes;
+      delete p;
+      return fail(LAMINO_E_BUDGET, "lamino_plan: workspace %zu bytes exceeds budget %zu", need,
+                  o.hbm_budget);
+    }
+  }
+  build_tables(p);
+  p->d_tables = nullptr;
+  p->d_work = nullptr;
+  p->bound = false;
+  *out = p;
+  return LAMINO_OK;
+}
+
+int lamino_plan_sizes(const lamino_plan_t* p, size_t* table_bytes, size_t* work_bytes) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_sizes: NULL plan");
+  if (table_bytes) *table_bytes = p->table_bytes;
+  if (work_bytes) *work_bytes = p->work_bytes;
+  return LAMINO_OK;
+}
+
+int lamino_plan_info(const lamino_plan_t* p, lamino_info* info) {
+  if (!p || !info) return fail(LAMINO_E_INVALID, "lamino_plan_info: NULL argument");
+  info->h_p = p->h_p;
+  info->w_p = p->w_p;
+  info->n_slab = p->n_slab;
+  info->grid = p->grid;
+  info->kernel_m = p->M;
+  info->beta = p->beta;
+  info->z_chunk = p->z_chunk;
+  info->slab_chunk = p->slab_chunk;
+  info->theta_chunk = p->theta_chunk;
+  info->table_bytes = p->table_bytes;
+  info->work_bytes = p->work_bytes;
+  info->off_spectra = p->off_D;
+  info->bytes_spectra = p->bytes_D;
+  info->off_slabs = p->off_g;
+  info->bytes_slabs = p->bytes_g;
+  return LAMINO_OK;
+}
+
+int lamino_plan_bind(lamino_plan_t* p, void* d_tables, void* d_work, void* stream) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_bind: NULL plan");
+  if (!d_tables || !d_work) return fail(LAMINO_E_INVALID, "lamino_plan_bind: NULL buffer");
+  if (((uintptr_t)d_tables & 255) || ((uintptr_t)d_work & 255))
+    return fail(LAMINO_E_INVALID, "lamino_plan_bind: buffers must be 256-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(d_tables, p->host_tables.data(), p->table_bytes,
+                                hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "lamino_plan_bind: table upload");
+  // the host staging copy must stay valid until the copy has run
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "lamino_plan_bind: synchronise");
+  p->d_tables = d_tables;
+  p->d_work = d_work;
+  p->bound = true;
+  return LAMINO_OK;
+}
+
+static int check_call(const lamino_plan_t* p, const void* a, const void* b, const char* who) {
+  if (!p) return fail(LAMINO_E_INVALID, "%s: NULL plan", who);
+  if (!p->bound) return fail(LAMINO_E_UNBOUND, "%s: plan is not bound", who);
+  if (!a || !b) return fail(LAMINO_E_INVALID, "%s: NULL data or volume pointer", who);
+  return LAMINO_OK;
+}
+
+int lamino_fbp(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {
+  const int c = check_call(p, d_data, d_vol, "lamino_fbp");
+  if (c) return c;
+  hipError_t e = lam::run_backprojection(p, d_data, d_vol, true, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp");
+}
+
+int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {
+  const int c = check_call(p, d_data, d_vol, "lamino_adj");
+  if (c) return c;
+  hipError_t e = lam::run_backprojection(p, d_data, d_vol, false, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_adj");
+}
+
+int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* stream) {
+  const int c = check_call(p, d_vol, d_data, "lamino_fwd");
+  if (c) return c;
+  hipError_t e = lam::run_forward(p, d_vol, d_data, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fwd");
+}
+
+int lamino_plan_destroy(lamino_plan_t* p) {
+  delete p;
+  return LAMINO_OK;
+}
+
+const char* lamino_strerror(int status) {
+  switch (status) {
+    case LAMINO_OK: return "success";
+    case LAMINO_E_INVALID: return "invalid argument";
+    case LAMINO_E_UNSUPPORTED: return "unsupported size";
+    case LAMINO_E_BUDGET: return "workspace exceeds the memory budget";
+    case LAMINO_E_HIP: return "HIP runtime error";
+    case LAMINO_E_UNBOUND: return "plan not bound to device buffers";
+    default: return "unknown status";
+  }
+}
+
+const char* lamino_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

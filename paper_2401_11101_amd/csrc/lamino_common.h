@@ -1,0 +1,170 @@
+// Shared host/device helpers of the laminography library.
+//
+// Everything here is plain arithmetic on indices and float2 values, usable
+// from the gfx950 kernels and from host unit tests of the index logic.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#define LAM_HD __host__ __device__ __forceinline__
+
+namespace lam {
+
+// ---------------------------------------------------------------- complex
+LAM_HD float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+LAM_HD float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+LAM_HD float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+LAM_HD float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+LAM_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+LAM_HD float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+LAM_HD float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
+
+LAM_HD int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+// ------------------------------------------------------------ FFT passes
+// Stockham autosort FFT of length N = 2^log2N, radix 4 passes followed by
+// one radix-2 pass when log2N is odd.  A pass with sub-transform size Ns
+// maps butterfly j (0 <= j < N/R) from positions j + r N/R to positions
+// (j - j%Ns) R + j%Ns + r Ns after twiddling by w^(r (j%Ns)),
+// w = exp(-+2 pi i / (Ns R)).  The twiddle table holds
+// tw[t] = exp(-2 pi i t / Nmax), Nmax = 2^log2max >= N.
+
+struct FftPass {
+  int radix;   // 4 or 2
+  int log2Ns;  // log2 of the sub-transform size before this pass
+};
+
+LAM_HD int fft_num_passes(int log2N) { return (log2N >> 1) + (log2N & 1); }
+
+LAM_HD FftPass fft_pass(int log2N, int p) {
+  FftPass f;
+  const int n4 = log2N >> 1;
+  if (p < n4) {
+    f.radix = 4;
+    f.log2Ns = 2 * p;
+  } else {
+    f.radix = 2;
+    f.log2Ns = 2 * n4;
+  }
+  return f;
+}
+
+LAM_HD float2 twiddle(const float2* tw, int idx, bool inv) {
+  float2 t = tw[idx];
+  return inv ? cconj(t) : t;
+}
+
+// Inputs of butterfly j of a radix-4 pass over one transform at `a`.
+LAM_HD void r4_load(const float2* a, int N, int j, float2 v[4]) {
+  const int q = N >> 2;
+  v[0] = a[j];
+  v[1] = a[j + q];
+  v[2] = a[j + 2 * q];
+  v[3] = a[j + 3 * q];
+}
+
+LAM_HD void r4_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[4]) {
+  const int Ns = 1 << log2Ns;
+  const int k = j & (Ns - 1);
+  if (Ns > 1) {
+    const int sh = log2max - (log2Ns + 2);
+    v[1] = cmul(v[1], twiddle(tw, k << sh, inv));
+    v[2] = cmul(v[2], twiddle(tw, (2 * k) << sh, inv));
+    v[3] = cmul(v[3], twiddle(tw, (3 * k) << sh, inv));
+  }
+  const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+  const float2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
+  const float2 rot = inv ? mul_pi(d13) : mul_mi(d13);
+  const int o = ((j - k) << 2) + k;
+  a[o] = cadd(s02, s13);
+  a[o + Ns] = cadd(d02, rot);
+  a[o + 2 * Ns] = csub(s02, s13);
+  a[o + 3 * Ns] = csub(d02, rot);
+}
+
+LAM_HD void r2_load(const float2* a, int N, int j, float2 v[2]) {
+  v[0] = a[j];
+  v[1] = a[j + (N >> 1)];
+}
+
+LAM_HD void r2_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[2]) {
+  const int Ns = 1 << log2Ns;
+  const int k = j & (Ns - 1);
+  if (Ns > 1) v[1] = cmul(v[1], twiddle(tw, k << (log2max - (log2Ns + 1)), inv));
+  const int o = ((j - k) << 1) + k;
+  a[o] = cadd(v[0], v[1]);
+  a[o + Ns] = csub(v[0], v[1]);
+}
+
+// ---------------------------------------------------- sample positions
+// Slab l of the tilted grid (eq:uneqspace): the sample of angle theta and
+// detector frequency m sits at (X, Y) = N_g (xi1, xi2) grid cells with
+//   X = (N_g / w_p) cos(t) m + (N_g l sin(p) / h_p) sin(t)
+//   Y = (N_g / w_p) sin(t) m - (N_g l sin(p) / h_p) cos(t).
+// Every kernel computes it with this function so that gridding and
+// interpolation see bit-identical positions.
+LAM_HD void sample_pos(float ncw, float gcl, float2 cs, int m, float& X, float& Y) {
+  const float fm = (float)m;
+  X = fmaf(ncw * cs.x, fm, gcl * cs.y);
+  Y = fmaf(ncw * cs.y, fm, -(gcl * cs.x));
+}
+
+// m-interval of samples whose coordinate a m + b lies in [lo, hi).
+// Conservative by one sample at each end; returns false if empty.
+LAM_HD bool coord_interval(float a, float b, float lo, float hi, int& mlo, int& mhi) {
+  if (fabsf(a) < 1e-6f) {
+    if (b >= lo - 1.0f && b < hi + 1.0f) {
+      mlo = -(1 << 30);
+      mhi = 1 << 30;
+      return true;
+    }
+    return false;
+  }
+  float t0 = (lo - b) / a, t1 = (hi - b) / a;
+  if (t0 > t1) {
+    const float t = t0;
+    t0 = t1;
+    t1 = t;
+  }
+  // clamp before the conversion so that nothing overflows an int
+  t0 = fmaxf(t0, -1.0e8f);
+  t1 = fminf(t1, 1.0e8f);
+  mlo = (int)floorf(t0) - 1;
+  mhi = (int)ceilf(t1) + 1;
+  return mlo <= mhi;
+}
+
+// Candidate samples of one angle for a tile copy [x0, x0 + ext) x
+// [y0, y0 + ext): returns the m-range [mlo, mhi] (inclusive) within the
+// stored frequencies -(w_p/2 - 1) .. w_p/2 - 1.
+LAM_HD bool tile_candidates(float ncw, float gcl, float2 cs, float x0, float y0, float extx,
+                            float exty, int half_m, int& mlo, int& mhi) {
+  int a0, a1, b0, b1;
+  if (!coord_interval(ncw * cs.x, gcl * cs.y, x0, x0 + extx, a0, a1)) return false;
+  if (!coord_interval(ncw * cs.y, -(gcl * cs.x), y0, y0 + exty, b0, b1)) return false;
+  mlo = a0 > b0 ? a0 : b0;
+  mhi = a1 < b1 ? a1 : b1;
+  if (mlo < -half_m) mlo = -half_m;
+  if (mhi > half_m) mhi = half_m;
+  return mlo <= mhi;
+}
+
+// Edge of the tiles that own samples in the adjoint gridding (spreading).
+LAM_HD int gridding_tile(int grid) { return grid < 32 ? grid : 32; }
+
+// Wrap an integer grid coordinate to [-N/2, N/2) (N a power of two).
+LAM_HD int wrap_centred(int k, int N) { return ((k + (N >> 1)) & (N - 1)) - (N >> 1); }
+
+}  // namespace lam

@@ -1,0 +1,69 @@
+// Internal plan layout and kernel launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lamino.h"
+
+namespace lam {
+
+// Parameters every kernel receives by value (device pointers into the
+// caller's table and workspace buffers).
+struct KParams {
+  int nz, n, n_theta, h, w;
+  int h_p, w_p, n_slab, grid, M;
+  int log2_hp, log2_wp, log2_grid, log2_twmax;
+  float beta;
+  float ncw;       // grid / w_p
+  float gs;        // grid * sin(phi) / h_p (per unit of l)
+  int data_dtype, storage_dtype;
+  const float2* trig;     // [n_theta] (cos, sin)
+  const float* filt;      // [w_p] transfer function incl. 1/(h_p w_p)
+  const float* deapod;    // [n] psi correction per axis
+  const float2* e_adj;    // [nz][n_slab] w_l exp(+2 pi i x3 l cos(phi)/h_p)
+  const float2* e_fwd;    // [n_slab][nz] exp(-2 pi i x3 l cos(phi)/h_p)
+  const float2* tw;       // [2^log2_twmax] exp(-2 pi i t / 2^log2_twmax)
+};
+
+}  // namespace lam
+
+struct lamino_plan_s {
+  // geometry
+  int nz, n, n_theta, h, w;
+  double tilt;
+  std::vector<double> theta;
+  lamino_opts opts;
+  // derived sizes
+  int h_p, w_p, n_slab, grid, M, tile;
+  double beta;
+  int z_chunk, slab_chunk, theta_chunk;
+  // table layout (bytes)
+  size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_e_adj, off_e_fwd, off_tw;
+  size_t table_bytes;
+  int log2_twmax;
+  // workspace layout (bytes)
+  size_t off_w1, off_D, off_G, off_Gp, off_g;
+  size_t bytes_w1, bytes_D, bytes_G, bytes_Gp, bytes_g;
+  size_t work_bytes;
+  std::vector<unsigned char> host_tables;
+  void* d_tables;
+  void* d_work;
+  bool bound;
+};
+
+namespace lam {
+
+KParams make_params(const lamino_plan_s* p, bool fbp_filter);
+size_t storage_bytes(int dtype);  // bytes of one stored complex value
+size_t data_bytes(int dtype);     // bytes of one real data value
+
+// The three operator pipelines (enqueue only).
+hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
+                              bool fbp_filter, hipStream_t s);
+hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
+                       hipStream_t s);
+
+}  // namespace lam

@@ -1,0 +1,882 @@
+// gfx950 kernels of the Fourier-route laminography operators.
+//
+// Backprojection / FBP (eq:fftadj with the filter of eq:recon):
+//   proj_cols_fwd  per projection: real column pairs -> h_p-point FFT along v
+//   proj_rows_fwd  per (projection, l): w_p-point FFT along u, filter,
+//                  store the spectrum slab-major D[l][theta][k]
+//   spread         per (slab, tile): Gaussian gridding of the slab's samples
+//                  into an LDS tile, no global atomics
+//   grid_rows_inv  per slab row: inverse N_g-point FFT along x1, crop
+//   grid_cols_adj  per slab column block: inverse FFT along x2, crop, psi
+//                  correction, store g[l][y][x]
+//   x3_adj         vol[z][col] = Re sum_l w_l exp(2 pi i x3 l cos(phi)/h_p) g[l][col]
+// Forward projection (eq:fftfwd) runs the transposes in reverse order:
+//   x3_fwd, grid_cols_fwd, grid_rows_fwd, interp, proj_rows_inv, proj_cols_inv.
+//
+// FFTs are Stockham radix-4/2 passes over LDS with twiddles from a table
+// computed in double precision on the host.  All arithmetic is float32;
+// stored spectra and slab planes may be float16 / bfloat16.
+#include "lamino_common.h"
+#include "lamino_internal.h"
+
+namespace lam {
+
+constexpr int NT = 256;        // threads per block
+constexpr int LDS_CPLX = 4096; // complex values per FFT block buffer (two buffers: 64 KB)
+constexpr int TILE_MAX = 64;   // gridding tile edge
+constexpr int SEG_THETA = 128; // angles per candidate pass
+constexpr int SEG_SLOTS = 9;   // periodic copies of a tile per angle
+
+// ------------------------------------------------------------ load/store
+__device__ __forceinline__ float2 ld_c(const void* p, size_t i, int dt) {
+  if (dt == LAMINO_F32) return reinterpret_cast<const float2*>(p)[i];
+  if (dt == LAMINO_F16) return __half22float2(reinterpret_cast<const __half2*>(p)[i]);
+  return __bfloat1622float2(reinterpret_cast<const __hip_bfloat162*>(p)[i]);
+}
+__device__ __forceinline__ void st_c(void* p, size_t i, float2 v, int dt) {
+  if (dt == LAMINO_F32) reinterpret_cast<float2*>(p)[i] = v;
+  else if (dt == LAMINO_F16) reinterpret_cast<__half2*>(p)[i] = __float22half2_rn(v);
+  else reinterpret_cast<__hip_bfloat162*>(p)[i] = __float22bfloat162_rn(v);
+}
+__device__ __forceinline__ float ld_r(const void* p, size_t i, int dt) {
+  if (dt == LAMINO_F32) return reinterpret_cast<const float*>(p)[i];
+  if (dt == LAMINO_F16) return __half2float(reinterpret_cast<const __half*>(p)[i]);
+  return __bfloat162float(reinterpret_cast<const __hip_bfloat16*>(p)[i]);
+}
+__device__ __forceinline__ void st_r(void* p, size_t i, float v, int dt) {
+  if (dt == LAMINO_F32) reinterpret_cast<float*>(p)[i] = v;
+  else if (dt == LAMINO_F16) reinterpret_cast<__half*>(p)[i] = __float2half_rn(v);
+  else reinterpret_cast<__hip_bfloat16*>(p)[i] = __float2bfloat16(v);
+}
+
+// ------------------------------------------------------------ block FFT
+// B transforms of length 2^log2N stored back to back in LDS at `a`
+// (B * N <= LDS_CPLX), with `b` as the ping-pong partner.  Returns the
+// buffer that holds the result.
+__device__ float2* block_fft(float2* a, float2* b, int log2N, int B,
+                             const float2* __restrict__ tw, int log2max, bool inv) {
+  const int N = 1 << log2N;
+  const int np = fft_num_passes(log2N);
+  for (int p = 0; p < np; ++p) {
+    const FftPass f = fft_pass(log2N, p);
+    if (f.radix == 4) {
+      const int per = N >> 2;
+      const int total = B * per;
+      for (int t = threadIdx.x; t < total; t += NT) {
+        const int bb = t >> (log2N - 2), j = t & (per - 1);
+        float2 v[4];
+        r4_load(a + bb * N, N, j, v);
+        r4_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
+      }
+    } else {
+      const int per = N >> 1;
+      const int total = B * per;
+      for (int t = threadIdx.x; t < total; t += NT) {
+        const int bb = t >> (log2N - 1), j = t & (per - 1);
+        float2 v[2];
+        r2_load(a + bb * N, N, j, v);
+        r2_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
+      }
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+__device__ __forceinline__ void lds_zero(float2* buf, int count) {
+  for (int e = threadIdx.x; e < count; e += NT) buf[e] = make_float2(0.f, 0.f);
+}
+
+// ====================================================== detector transforms
+// W1 layout: [theta_local][n_slab][w] float2.
+
+// Column pairs (c, c+1) of projection theta0 + blockIdx.y packed as one
+// complex h_p-point FFT along v; the two real spectra are separated by
+// Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
+__global__ __launch_bounds__(NT) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
+                                                      float2* __restrict__ w1, int theta0,
+                                                      int cp) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int c0 = blockIdx.x * 2 * cp;
+  const int hp = p.h_p;
+  lds_zero(buf, cp * hp);
+  __syncthreads();
+  const int wide = 2 * cp;
+  float* bf = reinterpret_cast<float*>(buf);
+  for (int e = threadIdx.x; e < p.h * wide; e += NT) {
+    const int r = e / wide, cl = e - r * wide;
+    const int c = c0 + cl;
+    const float v = c < p.w ? ld_r(data, ((size_t)th * p.h + r) * p.w + c, p.data_dtype) : 0.f;
+    const int pos = (r - p.h / 2) & (hp - 1);
+    bf[2 * ((cl >> 1) * hp + pos) + (cl & 1)] = v;
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, false);
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  for (int e = threadIdx.x; e < p.n_slab * wide; e += NT) {
+    const int l = e / wide, cl = e - l * wide;
+    const int c = c0 + cl;
+    if (c >= p.w) continue;
+    const float2* z = res + (cl >> 1) * hp;
+    const float2 zl = z[l], zm = cconj(z[(hp - l) & (hp - 1)]);
+    float2 x;
+    if ((cl & 1) == 0) x = cscale(cadd(zl, zm), 0.5f);        // (Z[l] + conj Z[-l]) / 2
+    else x = cscale(mul_mi(csub(zl, zm)), 0.5f);              // (Z[l] - conj Z[-l]) / 2i
+    w1[base + (size_t)l * p.w + c] = x;
+  }
+}
+
+// Rows l of the column spectra: w_p-point FFT along u, times the transfer
+// function, stored as D[l][theta][k] (k = m mod w_p).
+__global__ __launch_bounds__(NT) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
+                                                      void* __restrict__ D, const float* filt,
+                                                      int theta0, int rows) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int l0 = blockIdx.x * rows;
+  const int wp = p.w_p;
+  lds_zero(buf, rows * wp);
+  __syncthreads();
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  for (int e = threadIdx.x; e < rows * p.w; e += NT) {
+    const int b = e / p.w, c = e - b * p.w;
+    const int l = l0 + b;
+    if (l < p.n_slab) buf[b * wp + ((c - p.w / 2) & (wp - 1))] = w1[base + (size_t)l * p.w + c];
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, false);
+  for (int e = threadIdx.x; e < rows * wp; e += NT) {
+    const int b = e / wp, k = e - b * wp;
+    const int l = l0 + b;
+    if (l < p.n_slab)
+      st_c(D, ((size_t)l * p.n_theta + th) * wp + k, cscale(res[e], filt[k]), p.storage_dtype);
+  }
+}
+
+// Inverse of the row step (forward projection): D[l][theta][.] -> inverse
+// FFT along m -> detector columns, W1[theta_local][l][c].
+__global__ __launch_bounds__(NT) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
+                                                      float2* __restrict__ w1, int theta0,
+                                                      int rows) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int l0 = blockIdx.x * rows;
+  const int wp = p.w_p;
+  for (int e = threadIdx.x; e < rows * wp; e += NT) {
+    const int b = e / wp, k = e - b * wp;
+    const int l = l0 + b;
+    float2 v = make_float2(0.f, 0.f);
+    if (l < p.n_slab && k != (wp >> 1))  // the Nyquist bin is not part of the sum
+      v = ld_c(D, ((size_t)l * p.n_theta + th) * wp + k, p.storage_dtype);
+    buf[e] = v;
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, true);
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  for (int e = threadIdx.x; e < rows * p.w; e += NT) {
+    const int b = e / p.w, c = e - b * p.w;
+    const int l = l0 + b;
+    if (l < p.n_slab) w1[base + (size_t)l * p.w + c] = res[b * wp + ((c - p.w / 2) & (wp - 1))];
+  }
+}
+
+// Inverse of the column step: the half spectra of columns (c, c+1) are
+// completed by Hermitian symmetry (Nyquist bin zero, imaginary part of
+// l = 0 dropped), packed as Z = X_c + i X_{c+1}, inverse transformed along
+// v, and the real / imaginary parts scaled by 1/(h_p w_p) give the two
+// detector columns.
+__global__ __launch_bounds__(NT) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
+                                                      void* __restrict__ data, int theta0,
+                                                      int cp, float scale) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int c0 = blockIdx.x * 2 * cp;
+  const int hp = p.h_p;
+  lds_zero(buf, cp * hp);
+  __syncthreads();
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  for (int e = threadIdx.x; e < p.n_slab * cp; e += NT) {
+    const int l = e / cp, pp = e - l * cp;
+    const int ca = c0 + 2 * pp, cb = ca + 1;
+    const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
+    const float2 xb = cb < p.w ? w1[base + (size_t)l * p.w + cb] : make_float2(0.f, 0.f);
+    float2* z = buf + pp * hp;
+    if (l == 0) {
+      z[0] = make_float2(xa.x, xb.x);
+    } else {
+      z[l] = make_float2(xa.x - xb.y, xa.y + xb.x);
+      z[hp - l] = make_float2(xa.x + xb.y, xb.x - xa.y);
+    }
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, true);
+  const int wide = 2 * cp;
+  const float* bf = reinterpret_cast<const float*>(res);
+  for (int e = threadIdx.x; e < p.h * wide; e += NT) {
+    const int r = e / wide, cl = e - r * wide;
+    const int c = c0 + cl;
+    if (c >= p.w) continue;
+    const int pos = (r - p.h / 2) & (hp - 1);
+    st_r(data, ((size_t)th * p.h + r) * p.w + c, bf[2 * ((cl >> 1) * hp + pos) + (cl & 1)] * scale,
+         p.data_dtype);
+  }
+}
+
+// ================================================================ gridding
+// Candidate list shared by spreading and interpolation: for SEG_THETA
+// angles at a time, each angle contributes up to SEG_SLOTS m-intervals (one
+// per periodic copy of the tile that its sample line can reach).
+struct SegLists {
+  int pre[SEG_THETA * SEG_SLOTS + 1];
+  int info[SEG_THETA * SEG_SLOTS];  // theta | (sx+1) << 16 | (sy+1) << 18
+  int mlo[SEG_THETA * SEG_SLOTS];
+  int tot[SEG_THETA];
+};
+
+// Build the lists for angles [th0, th0 + SEG_THETA); returns the sample
+// count.  margin_lo / ext: the box [x0 + sx N_g - margin_lo, ... + ext).
+__device__ int build_segments(SegLists& S, const KParams& p, int th0, float gcl, int X0, int Y0,
+                              float margin_lo, float ext) {
+  const int tid = threadIdx.x;
+  const int half_m = (p.w_p >> 1) - 1;
+  int mine = 0;
+  if (tid < SEG_THETA) {
+    const int th = th0 + tid;
+    int q = 0;
+    if (th < p.n_theta) {
+      const float2 cs = p.trig[th];
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          int mlo, mhi;
+          if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid) - margin_lo,
+                              (float)(Y0 + sy * p.grid) - margin_lo, ext, ext, half_m, mlo, mhi)) {
+            S.info[tid * SEG_SLOTS + q] = th | ((sx + 1) << 16) | ((sy + 1) << 18);
+            S.mlo[tid * SEG_SLOTS + q] = mlo;
+            S.pre[tid * SEG_SLOTS + q] = mhi - mlo + 1;  // count for now
+            mine += mhi - mlo + 1;
+            ++q;
+          }
+        }
+    }
+    for (; q < SEG_SLOTS; ++q) S.pre[tid * SEG_SLOTS + q] = 0;
+    S.tot[tid] = mine;
+  }
+  __syncthreads();
+  // inclusive scan of the per-angle totals (Hillis-Steele)
+  for (int off = 1; off < SEG_THETA; off <<= 1) {
+    int v = 0;
+    if (tid < SEG_THETA && tid >= off) v = S.tot[tid - off];
+    __syncthreads();
+    if (tid < SEG_THETA) S.tot[tid] += v;
+    __syncthreads();
+  }
+  if (tid < SEG_THETA) {
+    int run = tid ? S.tot[tid - 1] : 0;
+    for (int q = 0; q < SEG_SLOTS; ++q) {
+      const int c = S.pre[tid * SEG_SLOTS + q];
+      S.pre[tid * SEG_SLOTS + q] = run;
+      run += c;
+    }
+  }
+  if (tid == 0) S.pre[SEG_THETA * SEG_SLOTS] = S.tot[SEG_THETA - 1];
+  __syncthreads();
+  return S.pre[SEG_THETA * SEG_SLOTS];
+}
+
+// Largest s with pre[s] <= i.
+__device__ __forceinline__ int find_segment(const SegLists& S, int i) {
+  int lo = 0, hi = SEG_THETA * SEG_SLOTS;  // pre[lo] <= i < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S.pre[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Gaussian weights exp(-beta d^2) at the 2M taps d = (1 - M) - f, ..., M - f
+// by the recurrence w_{i+1} = w_i r_i, r_{i+1} = r_i exp(-2 beta).
+template <int M>
+__device__ __forceinline__ void gauss_taps(float f, float beta, float e2b, float w[2 * M]) {
+  const float d0 = (float)(1 - M) - f;
+  w[0] = expf(-beta * d0 * d0);
+  float r = expf(-beta * (2.f * d0 + 1.f));
+#pragma unroll
+  for (int i = 1; i < 2 * M; ++i) {
+    w[i] = w[i - 1] * r;
+    r *= e2b;
+  }
+}
+
+// Adjoint USFFT step (3): spread the samples of slab (slab0 + blockIdx.y)
+// owned by tile blockIdx.x (wrapped base cell inside the tile, the same
+// ownership rule as interpolation) into the tile padded by M-1 cells on the
+// low side and M on the high side.  One wave per tile: samples are staged
+// 64 at a time (position, value, separable weights), then every lane takes
+// one tap of one sample, so a wave instruction never touches a cell twice
+// and a plain LDS read-modify-write is race free.  The padded tiles go to
+// Gp[slab_local][tile][P][P]; the row IFFT folds the overlapping halos.
+constexpr int SPT_MAX = 32;     // spread tile edge (owned cells)
+constexpr int SP_THETA = 32;    // angles per candidate pass
+
+template <int M>
+__global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
+                                               float2* __restrict__ Gp, int slab0, int tile) {
+  constexpr int W = 2 * M;
+  constexpr int PMAX = SPT_MAX + 2 * M - 1;
+  constexpr int NQ = (W * W + 63) / 64;
+  constexpr int NSEG = SP_THETA * SEG_SLOTS;
+  __shared__ float2 acc[PMAX * PMAX];
+  __shared__ int seg_pre[NSEG + 1];
+  __shared__ int seg_info[NSEG];
+  __shared__ int seg_mlo[NSEG];
+  __shared__ int seg_tot[SP_THETA];
+  __shared__ int st_base[64];
+  __shared__ float2 st_val[64];
+  __shared__ float st_wx[64 * W];
+  __shared__ float st_wy[64 * W];
+  const int lane = threadIdx.x;
+  const int P = tile + 2 * M - 1;
+  const int l = slab0 + blockIdx.y;
+  const int ntx = p.grid / tile;
+  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const int X0 = -(p.grid >> 1) + tx * tile;
+  const int Y0 = -(p.grid >> 1) + ty * tile;
+  const float gcl = p.gs * (float)l;
+  const float e2b = expf(-2.f * p.beta);
+  const int half_m = (p.w_p >> 1) - 1;
+  for (int e = lane; e < P * P; e += 64) acc[e] = make_float2(0.f, 0.f);
+  int toff[NQ], ti[NQ], tj[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int t = lane + 64 * q;
+    ti[q] = t % W;
+    tj[q] = t / W;
+    toff[q] = (t < W * W) ? tj[q] * P + ti[q] : -1;
+  }
+  for (int th0 = 0; th0 < p.n_theta; th0 += SP_THETA) {
+    __syncthreads();
+    // candidate m-intervals of the owner box of every periodic copy
+    if (lane < SP_THETA) {
+      const int th = th0 + lane;
+      int q = 0, mine = 0;
+      if (th < p.n_theta) {
+        const float2 cs = p.trig[th];
+        for (int sy = -1; sy <= 1; ++sy)
+          for (int sx = -1; sx <= 1; ++sx) {
+            int mlo, mhi;
+            if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid) - 1.f,
+                                (float)(Y0 + sy * p.grid) - 1.f, (float)(tile + 2),
+                                (float)(tile + 2), half_m, mlo, mhi)) {
+              seg_info[lane * SEG_SLOTS + q] = th | ((sx + 1) << 16) | ((sy + 1) << 18);
+              seg_mlo[lane * SEG_SLOTS + q] = mlo;
+              seg_pre[lane * SEG_SLOTS + q] = mhi - mlo + 1;
+              mine += mhi - mlo + 1;
+              ++q;
+            }
+          }
+      }
+      for (; q < SEG_SLOTS; ++q) seg_pre[lane * SEG_SLOTS + q] = 0;
+      seg_tot[lane] = mine;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      int run = 0;
+      for (int t = 0; t < SP_THETA; ++t) {
+        const int c = seg_tot[t];
+        seg_tot[t] = run;
+        run += c;
+      }
+      seg_pre[NSEG] = run;
+    }
+    __syncthreads();
+    if (lane < SP_THETA) {
+      int run = seg_tot[lane];
+      for (int q = 0; q < SEG_SLOTS; ++q) {
+        const int c = seg_pre[lane * SEG_SLOTS + q];
+        seg_pre[lane * SEG_SLOTS + q] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    const int total = seg_pre[NSEG];
+    for (int base = 0; base < total; base += 64) {
+      // stage the owned samples among the next 64 candidates
+      const int i = base + lane;
+      bool own = false;
+      int bxw = 0, byw = 0, th = 0, m = 0;
+      float X = 0.f, Y = 0.f;
+      if (i < total) {
+        int lo = 0, hi = NSEG;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (seg_pre[mid] <= i) lo = mid;
+          else hi = mid;
+        }
+        const int info = seg_info[lo];
+        th = info & 0xFFFF;
+        const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
+        m = seg_mlo[lo] + (i - seg_pre[lo]);
+        sample_pos(p.ncw, gcl, p.trig[th], m, X, Y);
+        // owned through this periodic copy only (copies may overlap when
+        // the tile spans the whole grid)
+        bxw = (int)floorf(X) - sx * p.grid - X0;
+        byw = (int)floorf(Y) - sy * p.grid - Y0;
+        own = bxw >= 0 && bxw < tile && byw >= 0 && byw < tile;
+      }
+      const unsigned long long mask = __ballot(own);
+      const int cnt = __popcll(mask);
+      const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+      if (own) {
+        float wx[W], wy[W];
+        gauss_taps<M>(X - floorf(X), p.beta, e2b, wx);
+        gauss_taps<M>(Y - floorf(Y), p.beta, e2b, wy);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+          st_wx[pos * W + k] = wx[k];
+          st_wy[pos * W + k] = wy[k];
+        }
+        st_base[pos] = byw * P + bxw;
+        st_val[pos] = ld_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)),
+                           p.storage_dtype);
+      }
+      __syncthreads();
+      // every lane one tap; one sample per step
+      for (int s = 0; s < cnt; ++s) {
+        const int b = st_base[s];
+        const float2 v = st_val[s];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (toff[q] >= 0) {
+            const float w = st_wx[s * W + ti[q]] * st_wy[s * W + tj[q]];
+            float2 g = acc[b + toff[q]];
+            g.x = fmaf(v.x, w, g.x);
+            g.y = fmaf(v.y, w, g.y);
+            acc[b + toff[q]] = g;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  float2* out = Gp + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * P * P;
+  for (int e = lane; e < P * P; e += 64) out[e] = acc[e];
+}
+
+// Forward USFFT step (3): interpolate slab (slab0 + blockIdx.y) of the grid
+// at the samples whose wrapped base cell floor(X), floor(Y) lies in tile
+// blockIdx.x; the padded tile is staged in LDS.  Each sample has exactly
+// one owner tile, so D is written once per sample.
+template <int M>
+__global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restrict__ G,
+                                               void* __restrict__ D, int slab0, int tile) {
+  constexpr int PMAX = TILE_MAX + 2 * M - 1;
+  __shared__ float2 st[PMAX * PMAX];
+  __shared__ SegLists S;
+  const int P = tile + 2 * M - 1;
+  const int l = slab0 + blockIdx.y;
+  const int ntx = p.grid / tile;
+  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const int X0 = -(p.grid >> 1) + tx * tile;
+  const int Y0 = -(p.grid >> 1) + ty * tile;
+  const float gcl = p.gs * (float)l;
+  const float e2b = expf(-2.f * p.beta);
+  const size_t gbase = (size_t)blockIdx.y * p.grid * p.grid;
+  for (int e = threadIdx.x; e < P * P; e += NT) {
+    const int yy = e / P, xx = e - yy * P;
+    const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
+    st[e] = G[gbase + (size_t)ky * p.grid + kx];
+  }
+  for (int th0 = 0; th0 < p.n_theta; th0 += SEG_THETA) {
+    __syncthreads();
+    const int total = build_segments(S, p, th0, gcl, X0, Y0, 1.0f, (float)(tile + 2));
+    for (int i = threadIdx.x; i < total; i += NT) {
+      const int s = find_segment(S, i);
+      const int info = S.info[s];
+      const int th = info & 0xFFFF;
+      const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
+      const int m = S.mlo[s] + (i - S.pre[s]);
+      float X, Y;
+      const float2 cs = p.trig[th];
+      sample_pos(p.ncw, gcl, cs, m, X, Y);
+      const float fXf = floorf(X), fYf = floorf(Y);
+      const int bx = (int)fXf - sx * p.grid - X0;
+      const int by = (int)fYf - sy * p.grid - Y0;
+      if (bx < 0 || bx >= tile || by < 0 || by >= tile) continue;  // not this tile's sample
+      float wx[2 * M], wy[2 * M];
+      gauss_taps<M>(X - fXf, p.beta, e2b, wx);
+      gauss_taps<M>(Y - fYf, p.beta, e2b, wy);
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < 2 * M; ++j) {
+        float2 row = make_float2(0.f, 0.f);
+        const float2* src = st + (by + j) * P + bx;
+#pragma unroll
+        for (int i2 = 0; i2 < 2 * M; ++i2) {
+          row.x = fmaf(wx[i2], src[i2].x, row.x);
+          row.y = fmaf(wx[i2], src[i2].y, row.y);
+        }
+        acc.x = fmaf(wy[j], row.x, acc.x);
+        acc.y = fmaf(wy[j], row.y, acc.y);
+      }
+      st_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)), acc, p.storage_dtype);
+    }
+  }
+}
+
+// ======================================================= slab 2D transforms
+// Grid layout: G[slab_local][k2][k1], index k mod N_g.  After the row pass
+// the first n entries of each row hold x1 = ix - n/2 (ix < n).
+
+// Inverse FFT along x1 of the gridded slab.  The grid is assembled on load
+// from the padded spread tiles: cell u (unwrapped, u = k + N_g/2) of tile
+// u / T sits at padded index u % T + M - 1; the halos of the neighbouring
+// tiles (one period either way) add at u % T + M - 1 -+ T.
+__global__ __launch_bounds__(NT) void k_grid_rows_inv(KParams p, const float2* __restrict__ Gp,
+                                                      float2* __restrict__ G, int rows, int tile) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int N = p.grid;
+  const int P = tile + 2 * p.M - 1;
+  const int nt = N / tile;
+  const int r0 = blockIdx.x * rows;
+  const float2* gp = Gp + (size_t)blockIdx.y * nt * nt * P * P;
+  for (int e = threadIdx.x; e < rows * N; e += NT) {
+    const int b = e / N, k1 = e - b * N;
+    const int r = r0 + b;
+    float2 sum = make_float2(0.f, 0.f);
+    if (r < N) {
+      const int u1 = (k1 + (N >> 1)) & (N - 1), u2 = (r + (N >> 1)) & (N - 1);
+      const int tx = u1 / tile, lx = u1 - tx * tile;
+      const int ty = u2 / tile, ly = u2 - ty * tile;
+      for (int sy = -1; sy <= 1; ++sy) {
+        const int py = ly + p.M - 1 + sy * tile;
+        if (py < 0 || py >= P) continue;
+        const int tyy = (ty - sy + nt) % nt;
+        for (int sx = -1; sx <= 1; ++sx) {
+          const int px = lx + p.M - 1 + sx * tile;
+          if (px < 0 || px >= P) continue;
+          const int txx = (tx - sx + nt) % nt;
+          sum = cadd(sum, gp[((size_t)(tyy * nt + txx) * P + py) * P + px]);
+        }
+      }
+    }
+    buf[e] = sum;
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, true);
+  float2* g = G + (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < rows * p.n; e += NT) {
+    const int b = e / p.n, ix = e - b * p.n;
+    if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
+                                                      void* __restrict__ g, int slab0, int cols) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int N = p.grid;
+  const int ix0 = blockIdx.x * cols;
+  const float2* gg = G + (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < cols * N; e += NT) {
+    const int k2 = e / cols, c = e - k2 * cols;
+    buf[c * N + k2] = (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, true);
+  const int l = slab0 + blockIdx.y;
+  for (int e = threadIdx.x; e < cols * p.n; e += NT) {
+    const int y = e / cols, c = e - y * cols;
+    const int ix = ix0 + c;
+    if (ix >= p.n) continue;
+    const float2 v = cscale(res[c * N + ((y - p.n / 2) & (N - 1))], p.deapod[ix] * p.deapod[y]);
+    st_c(g, ((size_t)l * p.n + y) * p.n + ix, v, p.storage_dtype);
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
+                                                      float2* __restrict__ G, int slab0, int cols) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int N = p.grid;
+  const int ix0 = blockIdx.x * cols;
+  const int l = slab0 + blockIdx.y;
+  lds_zero(buf, cols * N);
+  __syncthreads();
+  for (int e = threadIdx.x; e < cols * p.n; e += NT) {
+    const int y = e / cols, c = e - y * cols;
+    const int ix = ix0 + c;
+    if (ix >= p.n) continue;
+    const float2 v = ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype);
+    buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, false);
+  float2* gg = G + (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < cols * N; e += NT) {
+    const int k2 = e / cols, c = e - k2 * cols;
+    if (ix0 + c < p.n) gg[(size_t)k2 * N + ix0 + c] = res[c * N + k2];
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
+                                                      int rows) {
+  __shared__ float2 buf[2 * LDS_CPLX];
+  const int N = p.grid;
+  const int r0 = blockIdx.x * rows;
+  float2* g = G + (size_t)blockIdx.y * N * N;
+  lds_zero(buf, rows * N);
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * p.n; e += NT) {
+    const int b = e / p.n, ix = e - b * p.n;
+    if (r0 + b < N) buf[b * N + ((ix - p.n / 2) & (N - 1))] = g[(size_t)(r0 + b) * N + ix];
+  }
+  __syncthreads();
+  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, false);
+  for (int e = threadIdx.x; e < rows * N; e += NT) {
+    const int b = e / N;
+    if (r0 + b < N) g[(size_t)(r0 + b) * N + (e - b * N)] = res[e];
+  }
+}
+
+// ============================================================ x3 transform
+// vol[z][col] = sum_l Re(e_adj[z][l] g[l][col]), z in [z0, z0 + nzc).
+// Block: 64 z x 64 columns, thread 4 x 4 outputs, l in chunks of 16.
+constexpr int XT = 64, XK = 16;
+
+__global__ __launch_bounds__(NT) void k_x3_adj(KParams p, const void* __restrict__ g,
+                                               float* __restrict__ vol, int z0, int nzc) {
+  __shared__ float2 Es[XT][XK + 1];
+  __shared__ float2 Gs[XK][XT];
+  const int ncol = p.n * p.n;
+  const int col0 = blockIdx.x * XT;
+  const int zb = blockIdx.y * XT;
+  const int tc = threadIdx.x & 15, tz = threadIdx.x >> 4;
+  float acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+  for (int l0 = 0; l0 < p.n_slab; l0 += XK) {
+    for (int e = threadIdx.x; e < XT * XK; e += NT) {
+      const int zz = e / XK, ll = e - zz * XK;
+      const int z = z0 + zb + zz, l = l0 + ll;
+      Es[zz][ll] = (zb + zz < nzc && l < p.n_slab) ? p.e_adj[(size_t)z * p.n_slab + l]
+                                                    : make_float2(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < XT * XK; e += NT) {
+      const int ll = e / XT, cc = e - ll * XT;
+      const int l = l0 + ll, col = col0 + cc;
+      Gs[ll][cc] = (l < p.n_slab && col < ncol) ? ld_c(g, (size_t)l * ncol + col, p.storage_dtype)
+                                                 : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ll = 0; ll < XK; ++ll) {
+      float2 ev[4], gv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ev[a] = Es[tz * 4 + a][ll];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) gv[b] = Gs[ll][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[a][b] = fmaf(ev[a].x, gv[b].x, fmaf(-ev[a].y, gv[b].y, acc[a][b]));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int zz = zb + tz * 4 + a;
+    if (zz >= nzc) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = col0 + tc + 16 * b;
+      if (col < ncol) vol[(size_t)(z0 + zz) * ncol + col] = acc[a][b];
+    }
+  }
+}
+
+// ghat[l][col] = sum_z e_fwd[l][z] f[z][col]; block 64 l x 64 columns.
+__global__ __launch_bounds__(NT) void k_x3_fwd(KParams p, const float* __restrict__ f,
+                                               void* __restrict__ g) {
+  __shared__ float2 Es[XT][XK + 1];
+  __shared__ float Fs[XK][XT];
+  const int ncol = p.n * p.n;
+  const int col0 = blockIdx.x * XT;
+  const int lb = blockIdx.y * XT;
+  const int tc = threadIdx.x & 15, tl = threadIdx.x >> 4;
+  float2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
+  for (int z0 = 0; z0 < p.nz; z0 += XK) {
+    for (int e = threadIdx.x; e < XT * XK; e += NT) {
+      const int ll = e / XK, zz = e - ll * XK;
+      const int l = lb + ll, z = z0 + zz;
+      Es[ll][zz] = (l < p.n_slab && z < p.nz) ? p.e_fwd[(size_t)l * p.nz + z] : make_float2(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < XT * XK; e += NT) {
+      const int zz = e / XT, cc = e - zz * XT;
+      const int z = z0 + zz, col = col0 + cc;
+      Fs[zz][cc] = (z < p.nz && col < ncol) ? f[(size_t)z * ncol + col] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int zz = 0; zz < XK; ++zz) {
+      float2 ev[4];
+      float fv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ev[a] = Es[tl * 4 + a][zz];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fv[b] = Fs[zz][tc + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x = fmaf(ev[a].x, fv[b], acc[a][b].x);
+          acc[a][b].y = fmaf(ev[a].y, fv[b], acc[a][b].y);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int l = lb + tl * 4 + a;
+    if (l >= p.n_slab) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = col0 + tc + 16 * b;
+      if (col < ncol) st_c(g, (size_t)l * ncol + col, acc[a][b], p.storage_dtype);
+    }
+  }
+}
+
+// ================================================================ drivers
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+static int spread_tile(const KParams& p) { return p.grid <= 128 ? (p.grid < 32 ? p.grid : 32) : 64; }
+
+template <int M>
+static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns, int tile,
+                          hipStream_t s) {
+  const int tiles = (kp.grid / tile) * (kp.grid / tile);
+  hipLaunchKernelGGL(k_spread<M>, dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0, tile);
+}
+template <int M>
+static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, int ns, int tile,
+                          hipStream_t s) {
+  const int tiles = (kp.grid / tile) * (kp.grid / tile);
+  hipLaunchKernelGGL(k_interp<M>, dim3(tiles, ns), dim3(NT), 0, s, kp, G, D, s0, tile);
+}
+
+static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns,
+                            hipStream_t s) {
+  const int tile = gridding_tile(kp.grid);
+  switch (kp.M) {
+    case 2: launch_spread<2>(kp, D, G, s0, ns, tile, s); break;
+    case 3: launch_spread<3>(kp, D, G, s0, ns, tile, s); break;
+    case 4: launch_spread<4>(kp, D, G, s0, ns, tile, s); break;
+    case 5: launch_spread<5>(kp, D, G, s0, ns, tile, s); break;
+    case 6: launch_spread<6>(kp, D, G, s0, ns, tile, s); break;
+    case 7: launch_spread<7>(kp, D, G, s0, ns, tile, s); break;
+    default: launch_spread<8>(kp, D, G, s0, ns, tile, s); break;
+  }
+}
+static void interp_dispatch(const KParams& kp, const float2* G, void* D, int s0, int ns,
+                            hipStream_t s) {
+  const int tile = spread_tile(kp);
+  switch (kp.M) {
+    case 2: launch_interp<2>(kp, G, D, s0, ns, tile, s); break;
+    case 3: launch_interp<3>(kp, G, D, s0, ns, tile, s); break;
+    case 4: launch_interp<4>(kp, G, D, s0, ns, tile, s); break;
+    case 5: launch_interp<5>(kp, G, D, s0, ns, tile, s); break;
+    case 6: launch_interp<6>(kp, G, D, s0, ns, tile, s); break;
+    case 7: launch_interp<7>(kp, G, D, s0, ns, tile, s); break;
+    default: launch_interp<8>(kp, G, D, s0, ns, tile, s); break;
+  }
+}
+
+static inline char* wptr(const lamino_plan_s* p, size_t off) {
+  return static_cast<char*>(p->d_work) + off;
+}
+
+hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
+                              bool fbp_filter, hipStream_t s) {
+  const KParams kp = make_params(p, fbp_filter);
+  float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
+  void* D = wptr(p, p->off_D);
+  float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
+  float2* Gp = reinterpret_cast<float2*>(wptr(p, p->off_Gp));
+  void* g = wptr(p, p->off_g);
+  const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
+  const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
+  for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
+    const int nt = std::min(p->theta_chunk, p->n_theta - t0);
+    hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp, d_data,
+                       W1, t0, cp);
+    hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
+                       (const float2*)W1, D, kp.filt, t0, rows_w);
+  }
+  const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
+  const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
+  for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
+    const int ns = std::min(p->slab_chunk, p->n_slab - s0);
+    spread_dispatch(kp, D, Gp, s0, ns, s);
+    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp,
+                       (const float2*)Gp, G, rows_g, gridding_tile(p->grid));
+    hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
+                       (const float2*)G, g, s0, cols_g);
+  }
+  const int ncol = p->n * p->n;
+  for (int z0 = 0; z0 < p->nz; z0 += p->z_chunk) {
+    const int nzc = std::min(p->z_chunk, p->nz - z0);
+    hipLaunchKernelGGL(k_x3_adj, dim3(cdiv(ncol, XT), cdiv(nzc, XT)), dim3(NT), 0, s, kp,
+                       (const void*)g, d_vol, z0, nzc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data, hipStream_t s) {
+  const KParams kp = make_params(p, false);
+  float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
+  void* D = wptr(p, p->off_D);
+  float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
+  void* g = wptr(p, p->off_g);
+  const int ncol = p->n * p->n;
+  hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, XT), cdiv(p->n_slab, XT)), dim3(NT), 0, s, kp,
+                     d_vol, g);
+  const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
+  const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
+  for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
+    const int ns = std::min(p->slab_chunk, p->n_slab - s0);
+    hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
+                       (const void*)g, G, s0, cols_g);
+    hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp, G,
+                       rows_g);
+    interp_dispatch(kp, G, D, s0, ns, s);
+  }
+  const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
+  const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
+  const float scale = (float)(1.0 / ((double)p->h_p * p->w_p));
+  for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
+    const int nt = std::min(p->theta_chunk, p->n_theta - t0);
+    hipLaunchKernelGGL(k_proj_rows_inv, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
+                       (const void*)D, W1, t0, rows_w);
+    hipLaunchKernelGGL(k_proj_cols_inv, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp,
+                       (const float2*)W1, d_data, t0, cp, scale);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lam

@@ -1,0 +1,113 @@
+"""C-ABI checks that need no GPU: exports, host-side plan logic, index logic."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle.geometry import Geometry
+from paper_2401_11101_amd import _abi, build as _build
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lamino.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_abi.LIB_PATH) or not os.path.exists(_build.SELFTEST):
+        _build.build()
+    return _abi.load_library()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lamino_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "lamino_plan" in names and "lamino_fbp" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(_abi.EXPORTED) == names
+
+
+def _geom(nz=16, n=20, n_theta=12, h=14, w=18, tilt=0.5):
+    g = _abi.lamino_geom()
+    g.nz, g.n, g.n_theta, g.h, g.w, g.tilt = nz, n, n_theta, h, w, tilt
+    return g
+
+
+def _plan_status(geom, opts=None):
+    o = opts if opts is not None else _abi.lamino_opts_default()
+    h = ctypes.c_void_p()
+    st = _abi.load_library().lamino_plan(ctypes.byref(geom), ctypes.byref(o), ctypes.byref(h))
+    if st == 0:
+        _abi.lamino_plan_destroy(h)
+    return st
+
+
+def test_plan_sizes_match_conventions(lib):
+    for (nz, n, nt, h, w) in [(16, 20, 12, 14, 18), (64, 64, 64, 64, 64), (256, 256, 720, 256, 320)]:
+        plan = _abi.lamino_plan(_geom(nz, n, nt, h, w), _abi.lamino_opts_default())
+        info = _abi.lamino_plan_info(plan)
+        g = Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=0.5)
+        assert (info.h_p, info.w_p) == (g.h_p, g.w_p)
+        assert info.n_slab == g.h_p // 2
+        assert info.grid >= 2 * n and info.grid & (info.grid - 1) == 0
+        assert info.kernel_m == 5
+        R = info.grid / n
+        assert info.beta == pytest.approx(math.pi * (R - 0.5) / (R * info.kernel_m))
+        t, wb = _abi.lamino_plan_sizes(plan)
+        assert t == info.table_bytes and wb == info.work_bytes and t % 256 == 0
+        _abi.lamino_plan_destroy(plan)
+
+
+def test_plan_rejects_bad_geometry(lib):
+    assert _plan_status(_geom(nz=0)) == _abi.LAMINO_E_INVALID
+    assert _plan_status(_geom(n_theta=-3)) == _abi.LAMINO_E_INVALID
+    assert _plan_status(_geom(tilt=math.pi / 2)) == _abi.LAMINO_E_INVALID
+    assert _plan_status(_geom(tilt=float("nan"))) == _abi.LAMINO_E_INVALID
+    assert _plan_status(_geom(w=5000)) == _abi.LAMINO_E_UNSUPPORTED
+    assert _plan_status(_geom(n=3000)) == _abi.LAMINO_E_UNSUPPORTED
+    o = _abi.lamino_opts_default()
+    o.kernel_m = 1
+    assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID
+    o = _abi.lamino_opts_default()
+    o.storage_dtype = 7
+    assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID
+    o = _abi.lamino_opts_default()
+    o.hbm_budget = 1000
+    assert _plan_status(_geom(), o) == _abi.LAMINO_E_BUDGET
+    assert "budget" in _abi.lamino_last_error()
+    assert _abi.lamino_strerror(_abi.LAMINO_E_BUDGET)
+
+
+def test_budget_shrinks_chunks(lib):
+    o = _abi.lamino_opts_default()
+    full = _abi.lamino_plan(_geom(64, 128, 100, 64, 128), o)
+    fi = _abi.lamino_plan_info(full)
+    o.hbm_budget = fi.work_bytes - 1
+    small = _abi.lamino_plan(_geom(64, 128, 100, 64, 128), o)
+    si = _abi.lamino_plan_info(small)
+    assert si.work_bytes <= o.hbm_budget
+    assert si.slab_chunk < fi.slab_chunk or si.theta_chunk < fi.theta_chunk
+    _abi.lamino_plan_destroy(full)
+    _abi.lamino_plan_destroy(small)
+
+
+def test_calls_before_bind_fail_cleanly(lib):
+    plan = _abi.lamino_plan(_geom(), _abi.lamino_opts_default())
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp(plan, ctypes.c_void_p(16), ctypes.c_void_p(16), None)
+    assert e.value.code == _abi.LAMINO_E_UNBOUND
+    _abi.lamino_plan_destroy(plan)
+
+
+def test_host_index_logic_selftest(lib):
+    out = subprocess.run([_build.SELFTEST], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "fft ok" in out.stdout and "cand ok" in out.stdout

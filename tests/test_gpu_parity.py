@@ -1,0 +1,154 @@
+"""GPU parity: the HIP operators against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import TOL_F32, TOL_LOWP, dev, ellipsoid_data, rel, to_dev, to_np
+from oracle import filters, nudft
+from oracle.geometry import Geometry, freqs
+from paper_2401_11101_amd import Plan
+
+pytestmark = pytest.mark.gpu
+
+FILTERS = {"ramp": filters.RAMP, "shepp-logan": filters.SHEPP_LOGAN, "parzen": filters.PARZEN}
+
+
+def _pair(nz, n, nt, h, w, phi_deg, seed=0, **kw):
+    g = Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=np.deg2rad(phi_deg), theta=kw.pop("theta", None))
+    plan = Plan(nz, n, nt, h, w, g.phi, theta=g.theta, **kw)
+    rng = np.random.default_rng(seed)
+    return g, plan, rng.standard_normal((nz, n, n)), rng.standard_normal((nt, h, w))
+
+
+@pytest.mark.parametrize("filt", ["shepp-logan", "ramp", "parzen"])
+def test_fbp_small_ragged(filt):
+    # sizes that are not multiples of any tile or FFT block
+    g, plan, _, d = _pair(16, 20, 12, 14, 18, 30, filter=filt)
+    got = to_np(plan.fbp(to_dev(d)))
+    e = rel(got, nudft.fbp(d, g, FILTERS[filt]))
+    print(f"fbp {filt} rel-L2 {e:.2e}")
+    assert e < TOL_F32
+
+
+def test_adj_and_fwd_small_ragged():
+    g, plan, f, d = _pair(16, 20, 12, 14, 18, 30)
+    ea = rel(to_np(plan.adj(to_dev(d))), nudft.adjoint(d, g))
+    ef = rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g))
+    print(f"adj rel-L2 {ea:.2e}, fwd rel-L2 {ef:.2e}")
+    assert ea < TOL_F32 and ef < TOL_F32
+
+
+def test_stored_spectra_match_oracle():
+    # stage check of the detector transforms: D[l][theta][k] after L*
+    g, plan, _, d = _pair(10, 16, 9, 12, 20, 25)
+    plan.adj(to_dev(d))
+    D = plan.spectra().cpu().numpy()  # (n_slab, n_theta, w_p)
+    G = nudft.data_spectra(d, g)  # (T, L, M), l from -h_p/2+1
+    ls, ms = freqs(g.h_p), freqs(g.w_p)
+    ref = np.zeros_like(D)
+    for li, l in enumerate(ls):
+        if l >= 0:
+            ref[l][:, ms % g.w_p] = G[:, li, :]
+    assert np.abs(D - ref).max() < 1e-6 * np.abs(ref).max()
+
+
+def test_c1_plain_fbp_config():
+    # 64^3 volume, 64 angles on [0, 2 pi), tilt 30 deg, detector 64 x 64,
+    # 20 seeded ellipsoids, exact projections + 1% noise, Shepp-Logan.
+    g, _, d = ellipsoid_data(20, 64, 64, 64, 64, 64, np.deg2rad(30), 0.01)
+    plan = Plan(64, 64, 64, 64, 64, g.phi)
+    got = to_np(plan.fbp(to_dev(d)))
+    e = rel(got, nudft.fbp(d, g, filters.SHEPP_LOGAN))
+    print(f"c1 fbp vs exact Fourier FBP rel-L2 {e:.2e}")
+    assert e < TOL_F32
+
+
+def test_adjoint_identity_on_gpu():
+    _, plan, f, d = _pair(48, 64, 40, 48, 64, 20, seed=3)
+    F, Dd = to_dev(f), to_dev(d)
+    Lf = plan.fwd(F).double()
+    Ltd = plan.adj(Dd).double()
+    a = float((Lf * Dd.double()).sum())
+    b = float((F.double() * Ltd).sum())
+    e = abs(a - b) / (float(Lf.norm()) * float(Dd.double().norm()))
+    print(f"adjoint mismatch {e:.2e}")
+    assert e < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_low_precision_storage(storage):
+    g, ells, d = ellipsoid_data(20, 32, 40, 48, 32, 40, np.deg2rad(25), 0.005)
+    plan = Plan(32, 40, 48, 32, 40, g.phi, storage_dtype=storage)
+    e_fbp = rel(to_np(plan.fbp(to_dev(d))), nudft.fbp(d, g, filters.SHEPP_LOGAN))
+    f = np.random.default_rng(5).uniform(size=(32, 40, 40))
+    e_fwd = rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g))
+    print(f"{storage} storage: fbp rel-L2 {e_fbp:.2e}, fwd rel-L2 {e_fwd:.2e}")
+    assert e_fbp < TOL_LOWP and e_fwd < TOL_LOWP
+
+
+@pytest.mark.parametrize("data_dtype", ["f16", "bf16"])
+def test_low_precision_data(data_dtype):
+    g, plan, f, _ = _pair(12, 16, 10, 12, 16, 30, data_dtype=data_dtype)
+    td = torch.float16 if data_dtype == "f16" else torch.bfloat16
+    d = np.random.default_rng(2).standard_normal((10, 12, 16))
+    dq = torch.tensor(d, dtype=td).double().numpy()  # the values the GPU sees
+    assert rel(to_np(plan.fbp(to_dev(dq, td))), nudft.fbp(dq, g)) < TOL_F32
+    out = plan.fwd(to_dev(f))
+    assert out.dtype == td
+    assert rel(to_np(out), nudft.forward(f, g)) < TOL_LOWP
+
+
+def test_chunking_does_not_change_results():
+    g, plan, f, d = _pair(20, 24, 30, 16, 24, 30)
+    small = Plan(20, 24, 30, 16, 24, g.phi, z_chunk=7, slab_chunk=3, theta_chunk=4)
+    a, b = to_np(plan.fbp(to_dev(d))), to_np(small.fbp(to_dev(d)))
+    assert rel(b, a) < 1e-6
+    a, b = to_np(plan.fwd(to_dev(f))), to_np(small.fwd(to_dev(f)))
+    assert rel(b, a) < 1e-6
+
+
+@pytest.mark.parametrize(
+    "nz, n, nt, h, w, phi",
+    [(1, 1, 1, 1, 1, 30), (3, 5, 2, 3, 7, 0), (8, 9, 7, 5, 11, 45), (4, 33, 3, 6, 40, 10),
+     (9, 17, 5, 9, 17, -35)],
+)
+def test_edge_sizes(nz, n, nt, h, w, phi):
+    g, plan, f, d = _pair(nz, n, nt, h, w, phi)
+    rf = nudft.forward(f, g)
+    ra = nudft.adjoint(d, g)
+    ef = rel(to_np(plan.fwd(to_dev(f))), rf) if np.linalg.norm(rf) > 0 else 0.0
+    ea = rel(to_np(plan.adj(to_dev(d))), ra) if np.linalg.norm(ra) > 0 else 0.0
+    print(f"edge {nz, n, nt, h, w, phi}: fwd {ef:.2e} adj {ea:.2e}")
+    assert ef < TOL_F32 and ea < TOL_F32
+
+
+def test_arbitrary_angles():
+    th = np.sort(np.random.default_rng(9).uniform(0, 2 * np.pi, 11))
+    g, plan, f, d = _pair(10, 14, 11, 10, 14, 20, theta=th)
+    assert rel(to_np(plan.adj(to_dev(d))), nudft.adjoint(d, g)) < TOL_F32
+    assert rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g)) < TOL_F32
+
+
+def test_repeat_calls_are_stable():
+    _, plan, _, d = _pair(16, 24, 16, 16, 24, 30)
+    D = to_dev(d)
+    a = to_np(plan.fbp(D))
+    for _ in range(3):
+        assert rel(to_np(plan.fbp(D)), a) < 1e-6
+
+
+def test_c2_full_size_sampled_columns():
+    # 256^3 volume, 400 angles, tilt 25 deg, 256 x 256 detector: the bench
+    # workload and launch configuration; columns checked one by one.
+    nz = n = h = w = 256
+    nt = 400
+    g, _, d = ellipsoid_data(50, nz, n, nt, h, w, np.deg2rad(25), 0.005)
+    plan = Plan(nz, n, nt, h, w, g.phi)
+    vol = to_np(plan.fbp(to_dev(d)))
+    G = nudft.filter_spectra(nudft.data_spectra_fft(d, g), g, filters.SHEPP_LOGAN)
+    ys = np.array([0, 77, 128, 201, 255])
+    xs = np.array([3, 128, 64, 250, 255])
+    ref = nudft.backproject_columns(G, g, ys, xs)
+    e = rel(vol[:, ys, xs], ref)
+    print(f"c2 sampled columns rel-L2 {e:.2e}")
+    assert e < TOL_F32

@@ -154,3 +154,11 @@ def test_backproject_columns_matches_full():
     ys, xs = np.array([0, 5, 13]), np.array([2, 9, 13])
     cols = nudft.backproject_columns(G, g, ys, xs)
     assert np.abs(cols - full[:, ys, xs]).max() < 1e-12 * np.abs(full).max()
+
+
+def test_fft_spectra_match_explicit_sums():
+    g = _geom()
+    d = np.random.default_rng(8).standard_normal((g.n_theta, g.h, g.w))
+    G = nudft.data_spectra(d, g)
+    assert np.abs(nudft.data_spectra_fft(d, g) - G).max() < 1e-14
+    assert np.abs(nudft.data_spectra_fft(d, g, half=True) - G[:, g.h_p // 2 - 1:, :]).max() < 1e-14
