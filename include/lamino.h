@@ -78,7 +78,7 @@ typedef struct {
                          arithmetic is always float32                         */
   int filter;         /* lamino_filter used by lamino_fbp                      */
   double pad_u, pad_v;/* detector padding factors (>= 1), default 2           */
-  int kernel_m;       /* Gaussian half-width M in grid cells (1..8); 0 picks
+  int kernel_m;       /* Gaussian half-width M in grid cells (2..8); 0 picks
                          5 for F32 storage and 3 for F16/BF16 storage          */
   int z_chunk;        /* x3-transform output slices per launch; 0 = nz         */
   int slab_chunk;     /* frequency slabs gridded per pass; 0 = automatic       */
@@ -90,7 +90,7 @@ typedef struct {
 typedef struct {
   int h_p, w_p;       /* padded detector                                      */
   int n_slab;         /* stored frequency slabs l = 0 .. h_p/2 - 1             */
-  int grid;           /* per-slab USFFT grid N_g (power of two >= 2 n)        */
+  int grid;           /* per-slab USFFT grid N_g: power of two >= max(32, 2n) */
   int kernel_m;       /* Gaussian half-width M                                */
   double beta;        /* Gaussian exponent: phi(t) = exp(-beta t^2), t in cells*/
   int z_chunk, slab_chunk, theta_chunk;
@@ -139,6 +139,27 @@ int lamino_fwd(const lamino_plan_t* plan, const float* d_vol, void* d_data, void
 /* Adjoint (eq:adj via eq:fftadj): vol = L* d, the exact transpose of
  * lamino_fwd.  Arguments as lamino_fbp. */
 int lamino_adj(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
+/* Stages reported by lamino_plan_stage_times. */
+enum {
+  LAMINO_STAGE_DETECTOR = 0, /* per-projection 2D FFTs and filter          */
+  LAMINO_STAGE_GRIDDING = 1, /* USFFT spreading (L*, FBP) / interpolation (L) */
+  LAMINO_STAGE_SLAB = 2,     /* per-slab 2D FFTs, crop, psi correction     */
+  LAMINO_STAGE_X3 = 3,       /* transform along x3                          */
+  LAMINO_NSTAGE = 4
+};
+
+/* Turn per-stage timing of later calls on (enable != 0) or off.  When on,
+ * every call records HIP events on its own stream around each stage's
+ * kernels (a small overhead per launch).  Host-only. */
+int lamino_plan_profile(lamino_plan_t* plan, int enable);
+
+/* Accumulated device milliseconds and kernel-launch counts per stage over
+ * the calls made while timing was on; ms and launches are arrays of
+ * LAMINO_NSTAGE entries (either may be NULL).  Waits for the recorded
+ * events.  reset != 0 clears the accumulators afterwards.  Errors:
+ * E_INVALID, E_HIP. */
+int lamino_plan_stage_times(lamino_plan_t* plan, double* ms, int* launches, int reset);
 
 /* Free the host plan (device buffers stay with the caller). NULL is ok. */
 int lamino_plan_destroy(lamino_plan_t* plan);

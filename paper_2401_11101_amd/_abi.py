@@ -28,6 +28,8 @@ EXPORTED = (
     "lamino_fbp",
     "lamino_fwd",
     "lamino_adj",
+    "lamino_plan_profile",
+    "lamino_plan_stage_times",
     "lamino_plan_destroy",
     "lamino_strerror",
     "lamino_last_error",
@@ -112,13 +114,16 @@ def load_library(path=LIB_PATH):
     lib.lamino_fbp.argtypes = [P, P, P, P]
     lib.lamino_fwd.argtypes = [P, P, P, P]
     lib.lamino_adj.argtypes = [P, P, P, P]
+    lib.lamino_plan_profile.argtypes = [P, ctypes.c_int]
+    lib.lamino_plan_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_int]
     lib.lamino_plan_destroy.argtypes = [P]
     lib.lamino_strerror.argtypes = [ctypes.c_int]
     lib.lamino_strerror.restype = ctypes.c_char_p
     lib.lamino_last_error.argtypes = []
     lib.lamino_last_error.restype = ctypes.c_char_p
     for name in ("lamino_plan", "lamino_plan_sizes", "lamino_plan_info", "lamino_plan_bind",
-                 "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy"):
+                 "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
+                 "lamino_plan_profile", "lamino_plan_stage_times"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -168,6 +173,22 @@ def lamino_fwd(plan, d_vol, d_data, stream):
 
 def lamino_adj(plan, d_data, d_vol, stream):
     _check(load_library().lamino_adj(plan, d_data, d_vol, stream), "lamino_adj")
+
+
+NSTAGE = 4
+STAGE_NAMES = ("detector", "gridding", "slab", "x3")
+
+
+def lamino_plan_profile(plan, enable):
+    _check(load_library().lamino_plan_profile(plan, int(bool(enable))), "lamino_plan_profile")
+
+
+def lamino_plan_stage_times(plan, reset=False):
+    """{stage: (milliseconds, launches)} accumulated while profiling was on."""
+    ms = (ctypes.c_double * NSTAGE)()
+    n = (ctypes.c_int * NSTAGE)()
+    _check(load_library().lamino_plan_stage_times(plan, ms, n, int(bool(reset))), "lamino_plan_stage_times")
+    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(NSTAGE)}
 
 
 def lamino_plan_destroy(plan):

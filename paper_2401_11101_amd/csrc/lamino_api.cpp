@@ -50,22 +50,13 @@ double window(double k, int kind) {
   return 0.0;
 }
 
-constexpr size_t kChunkTarget = 128u << 20;  // bytes per chunked intermediate
-
-// Bytes of one slab's padded spreading tiles (tile + 2M - 1 per edge).
-size_t padded_slab_bytes(const lamino_plan_s* p) {
-  const size_t t = lam::gridding_tile(p->grid);
-  const size_t P = t + 2 * p->M - 1;
-  const size_t nt = p->grid / t;
-  return nt * nt * P * P * 8;
-}
+constexpr size_t kChunkTarget = 512u << 20;  // bytes per chunked intermediate
 
 void layout_work(lamino_plan_s* p) {
   const size_t sb = lam::storage_bytes(p->opts.storage_dtype);
   p->bytes_w1 = (size_t)p->theta_chunk * p->n_slab * p->w * 8;
   p->bytes_D = (size_t)p->n_slab * p->n_theta * p->w_p * sb;
   p->bytes_G = (size_t)p->slab_chunk * p->grid * p->grid * 8;
-  p->bytes_Gp = (size_t)p->slab_chunk * padded_slab_bytes(p);
   p->bytes_g = (size_t)p->n_slab * p->n * p->n * sb;
   size_t off = 0;
   p->off_w1 = off;
@@ -74,8 +65,6 @@ void layout_work(lamino_plan_s* p) {
   off += align256(p->bytes_D);
   p->off_G = off;
   off += align256(p->bytes_G);
-  p->off_Gp = off;
-  off += align256(p->bytes_Gp);
   p->off_g = off;
   off += align256(p->bytes_g);
   p->work_bytes = off;
@@ -188,9 +177,68 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   return k;
 }
 
+static hipEvent_t take_event(lamino_plan_s* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+StageTimer::StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch)
+    : p(const_cast<lamino_plan_s*>(plan)), s(stream), stage(stage_id), launches(nlaunch),
+      start(nullptr) {
+  if (!p->profiling) return;
+  start = take_event(p);
+  if (start) (void)hipEventRecord(start, s);
+}
+
+StageTimer::~StageTimer() {
+  if (!start) return;
+  hipEvent_t stop = take_event(p);
+  if (!stop) return;
+  (void)hipEventRecord(stop, s);
+  p->marks.push_back({stage, launches, start, stop});
+}
+
 }  // namespace lam
 
 extern "C" {
+
+int lamino_plan_profile(lamino_plan_t* p, int enable) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_profile: NULL plan");
+  p->profiling = enable != 0;
+  return LAMINO_OK;
+}
+
+int lamino_plan_stage_times(lamino_plan_t* p, double* ms, int* launches, int reset) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_stage_times: NULL plan");
+  for (auto& m : p->marks) {
+    hipError_t e = hipEventSynchronize(m.stop);
+    if (e != hipSuccess) return hip_fail(e, "lamino_plan_stage_times");
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, m.start, m.stop);
+    if (e != hipSuccess) return hip_fail(e, "lamino_plan_stage_times");
+    p->stage_ms[m.stage] += t;
+    p->stage_launches[m.stage] += m.launches;
+    p->event_pool.push_back(m.start);
+    p->event_pool.push_back(m.stop);
+  }
+  p->marks.clear();
+  for (int i = 0; i < LAMINO_NSTAGE; ++i) {
+    if (ms) ms[i] = p->stage_ms[i];
+    if (launches) launches[i] = p->stage_launches[i];
+    if (reset) {
+      p->stage_ms[i] = 0.0;
+      p->stage_launches[i] = 0;
+    }
+  }
+  return LAMINO_OK;
+}
+
 
 void lamino_opts_default(lamino_opts* o) {
   if (!o) return;
@@ -247,7 +295,8 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   }
   p->w_p = pow2_at_least(std::ceil(o.pad_u * p->w));
   p->h_p = pow2_at_least(std::ceil(o.pad_v * p->h));
-  p->grid = std::max(16, pow2_at_least(2.0 * p->n));
+  // the gridding works on 32 x 32 matrix-core tiles
+  p->grid = std::max(32, pow2_at_least(2.0 * p->n));
   if (p->w_p < 2 || p->h_p < 2 || p->w_p > 4096 || p->h_p > 4096 || p->grid > 4096) {
     const int wp = p->w_p, hp = p->h_p, gr = p->grid;
     delete p;
@@ -264,7 +313,7 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   }
   p->tile = 0;
   p->z_chunk = o.z_chunk ? std::min(o.z_chunk, p->nz) : p->nz;
-  const size_t slab_bytes = (size_t)p->grid * p->grid * 8 + padded_slab_bytes(p);
+  const size_t slab_bytes = (size_t)p->grid * p->grid * 8;
   const size_t w1_bytes = (size_t)p->n_slab * p->w * 8;
   p->slab_chunk = o.slab_chunk ? std::min(o.slab_chunk, p->n_slab)
                                : (int)std::max<size_t>(1, std::min<size_t>(p->n_slab, kChunkTarget / slab_bytes));
@@ -274,7 +323,7 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   if (o.hbm_budget) {
     // shrink the chunked intermediates until the workspace fits
     while (p->work_bytes > o.hbm_budget && (p->slab_chunk > 1 || p->theta_chunk > 1)) {
-      if (p->bytes_G + p->bytes_Gp >= p->bytes_w1 && p->slab_chunk > 1) p->slab_chunk = (p->slab_chunk + 1) / 2;
+      if (p->bytes_G >= p->bytes_w1 && p->slab_chunk > 1) p->slab_chunk = (p->slab_chunk + 1) / 2;
       else if (p->theta_chunk > 1) p->theta_chunk = (p->theta_chunk + 1) / 2;
       else p->slab_chunk = (p->slab_chunk + 1) / 2;
       layout_work(p);
@@ -290,6 +339,11 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   p->d_tables = nullptr;
   p->d_work = nullptr;
   p->bound = false;
+  p->profiling = false;
+  for (int i = 0; i < LAMINO_NSTAGE; ++i) {
+    p->stage_ms[i] = 0.0;
+    p->stage_launches[i] = 0;
+  }
   *out = p;
   return LAMINO_OK;
 }
@@ -368,6 +422,13 @@ int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* s
 }
 
 int lamino_plan_destroy(lamino_plan_t* p) {
+  if (!p) return LAMINO_OK;
+  for (auto& m : p->marks) {
+    (void)hipEventSynchronize(m.stop);
+    (void)hipEventDestroy(m.start);
+    (void)hipEventDestroy(m.stop);
+  }
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   delete p;
   return LAMINO_OK;
 }

@@ -161,9 +161,6 @@ LAM_HD bool tile_candidates(float ncw, float gcl, float2 cs, float x0, float y0,
   return mlo <= mhi;
 }
 
-// Edge of the tiles that own samples in the adjoint gridding (spreading).
-LAM_HD int gridding_tile(int grid) { return grid < 32 ? grid : 32; }
-
 // Wrap an integer grid coordinate to [-N/2, N/2) (N a power of two).
 LAM_HD int wrap_centred(int k, int N) { return ((k + (N >> 1)) & (N - 1)) - (N >> 1); }
 

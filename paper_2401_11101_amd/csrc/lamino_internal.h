@@ -45,13 +45,24 @@ struct lamino_plan_s {
   size_t table_bytes;
   int log2_twmax;
   // workspace layout (bytes)
-  size_t off_w1, off_D, off_G, off_Gp, off_g;
-  size_t bytes_w1, bytes_D, bytes_G, bytes_Gp, bytes_g;
+  size_t off_w1, off_D, off_G, off_g;
+  size_t bytes_w1, bytes_D, bytes_G, bytes_g;
   size_t work_bytes;
   std::vector<unsigned char> host_tables;
   void* d_tables;
   void* d_work;
   bool bound;
+  // per-stage timing: event pairs recorded on the call's stream
+  bool profiling;
+  struct Mark {
+    int stage;
+    int launches;
+    hipEvent_t start, stop;
+  };
+  std::vector<Mark> marks;            // recorded, not yet collected
+  std::vector<hipEvent_t> event_pool; // created events available for reuse
+  double stage_ms[LAMINO_NSTAGE];
+  int stage_launches[LAMINO_NSTAGE];
 };
 
 namespace lam {
@@ -59,6 +70,16 @@ namespace lam {
 KParams make_params(const lamino_plan_s* p, bool fbp_filter);
 size_t storage_bytes(int dtype);  // bytes of one stored complex value
 size_t data_bytes(int dtype);     // bytes of one real data value
+
+// Stage bracketing (no-ops unless profiling is on).
+struct StageTimer {
+  lamino_plan_s* p;
+  hipStream_t s;
+  int stage, launches;
+  hipEvent_t start;
+  StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch);
+  ~StageTimer();
+};
 
 // The three operator pipelines (enqueue only).
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,

@@ -316,55 +316,120 @@ __device__ __forceinline__ void gauss_taps(float f, float beta, float e2b, float
   }
 }
 
-// Adjoint USFFT step (3): spread the samples of slab (slab0 + blockIdx.y)
-// owned by tile blockIdx.x (wrapped base cell inside the tile, the same
-// ownership rule as interpolation) into the tile padded by M-1 cells on the
-// low side and M on the high side.  One wave per tile: samples are staged
-// 64 at a time (position, value, separable weights), then every lane takes
-// one tap of one sample, so a wave instruction never touches a cell twice
-// and a plain LDS read-modify-write is race free.  The padded tiles go to
-// Gp[slab_local][tile][P][P]; the row IFFT folds the overlapping halos.
-constexpr int SPT_MAX = 32;     // spread tile edge (owned cells)
-constexpr int SP_THETA = 32;    // angles per candidate pass
+// Adjoint USFFT step (3) on the matrix cores.  For one 32 x 32 tile of the
+// slab grid, spreading is a sum of rank-one updates
+//     G_tile += wy_s (c_s wx_s)^T,
+// wy_s / wx_s the sample's Gaussian weights on the tile rows / columns (zero
+// outside its 2M taps), so a batch of K samples is one 32 x 32 x K matrix
+// product with the tile held in MFMA accumulators.  One wave per tile; it
+// visits every sample whose taps reach the tile (any periodic copy), stages
+// up to 64 of them in LDS, and feeds them 16 at a time.  Float32 storage
+// uses bf16 hi/lo splits (three products per component, ~2^-17 relative
+// error); float16 / bfloat16 storage uses one float16 / bfloat16 product.
+typedef unsigned short v8u __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
-template <int M>
+constexpr int SP_T = 32;       // tile edge = MFMA block
+constexpr int SP_THETA = 32;   // angles per candidate pass
+constexpr int SP_K = 16;       // samples per matrix product
+
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_to_f(unsigned h) { return __uint_as_float(h << 16); }
+// hi | lo << 16, hi + lo ~ x to ~2^-17
+__device__ __forceinline__ unsigned bf16_split(float x) {
+  const unsigned hi = bf16_rne(x);
+  const unsigned lo = bf16_rne(x - bf16_to_f(hi));
+  return hi | (lo << 16);
+}
+__device__ __forceinline__ unsigned f16_bits(float x) {
+  return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
+}
+
+template <int PREC>
+__device__ __forceinline__ v16f mfma16(v8u a, v8u b, v16f c) {
+  if (PREC == 1)
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a),
+                                                  __builtin_bit_cast(v8h, b), c, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+// One candidate sample of a lane: position, local tap-0 cell, value.
+struct SpreadCand {
+  bool use;
+  int lx, ly;
+  float X, Y;
+  float2 c;
+};
+
+// PREC 0: bf16 x3 (float32 storage), 1: float16 x1, 2: bfloat16 x1
+template <int M, int PREC>
 __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
-                                               float2* __restrict__ Gp, int slab0, int tile) {
+                                               float2* __restrict__ G, int slab0) {
   constexpr int W = 2 * M;
-  constexpr int PMAX = SPT_MAX + 2 * M - 1;
-  constexpr int NQ = (W * W + 63) / 64;
   constexpr int NSEG = SP_THETA * SEG_SLOTS;
-  __shared__ float2 acc[PMAX * PMAX];
   __shared__ int seg_pre[NSEG + 1];
   __shared__ int seg_info[NSEG];
   __shared__ int seg_mlo[NSEG];
   __shared__ int seg_tot[SP_THETA];
-  __shared__ int st_base[64];
-  __shared__ float2 st_val[64];
-  __shared__ float st_wx[64 * W];
-  __shared__ float st_wy[64 * W];
+  __shared__ int st_lx[64 + SP_K], st_ly[64 + SP_K];  // local column / row of tap 0
+  __shared__ unsigned st_a[64 * W];  // y-weights (PREC 0: hi | lo << 16, else 16-bit value)
+  __shared__ uint2 st_b[64 * W];     // c * x-weights: (re, im), same encoding
   const int lane = threadIdx.x;
-  const int P = tile + 2 * M - 1;
   const int l = slab0 + blockIdx.y;
-  const int ntx = p.grid / tile;
+  const int ntx = p.grid / SP_T;
   const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
-  const int X0 = -(p.grid >> 1) + tx * tile;
-  const int Y0 = -(p.grid >> 1) + ty * tile;
+  const int X0 = -(p.grid >> 1) + tx * SP_T;
+  const int Y0 = -(p.grid >> 1) + ty * SP_T;
   const float gcl = p.gs * (float)l;
   const float e2b = expf(-2.f * p.beta);
   const int half_m = (p.w_p >> 1) - 1;
-  for (int e = lane; e < P * P; e += 64) acc[e] = make_float2(0.f, 0.f);
-  int toff[NQ], ti[NQ], tj[NQ];
+  const int r = lane & 31;           // tile row of A / tile column of B held by this lane
+  const int kq = (lane >> 5) * 8;    // first of the lane's 8 samples within a group of 16
+  // periodic copies of the tile that the slab's samples can reach:
+  // |xi_perp| <= sqrt(1/4 + (l sin(phi) / h_p)^2) (eq:uneqspace)
+  const float reach = sqrtf(0.25f * (float)p.grid * (float)p.grid + gcl * gcl) + 2.f;
+  bool rx[3], ry[3];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const int t = lane + 64 * q;
-    ti[q] = t % W;
-    tj[q] = t / W;
-    toff[q] = (t < W * W) ? tj[q] * P + ti[q] : -1;
+  for (int s3 = 0; s3 < 3; ++s3) {
+    const float x0 = (float)(X0 + (s3 - 1) * p.grid - M), y0 = (float)(Y0 + (s3 - 1) * p.grid - M);
+    rx[s3] = x0 < reach && x0 + (float)(SP_T + 2 * M) > -reach;
+    ry[s3] = y0 < reach && y0 + (float)(SP_T + 2 * M) > -reach;
   }
+  v16f cre = {}, cim = {};
+
+  // candidate i of the current pass: segment search, position, value load
+  auto fetch = [&](int i, int total, SpreadCand& cd) {
+    cd.use = false;
+    cd.lx = cd.ly = 0;
+    cd.X = cd.Y = 0.f;
+    cd.c = make_float2(0.f, 0.f);
+    if (i >= total) return;
+    int lo = 0, hi = NSEG;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (seg_pre[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    const int info = seg_info[lo];
+    const int th = info & 0xFFFF;
+    const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
+    const int m = seg_mlo[lo] + (i - seg_pre[lo]);
+    sample_pos(p.ncw, gcl, p.trig[th], m, cd.X, cd.Y);
+    cd.lx = (int)floorf(cd.X) - M + 1 - sx * p.grid - X0;
+    cd.ly = (int)floorf(cd.Y) - M + 1 - sy * p.grid - Y0;
+    cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
+    if (cd.use)
+      cd.c = ld_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)), p.storage_dtype);
+  };
+
   for (int th0 = 0; th0 < p.n_theta; th0 += SP_THETA) {
     __syncthreads();
-    // candidate m-intervals of the owner box of every periodic copy
     if (lane < SP_THETA) {
       const int th = th0 + lane;
       int q = 0, mine = 0;
@@ -373,9 +438,10 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
         for (int sy = -1; sy <= 1; ++sy)
           for (int sx = -1; sx <= 1; ++sx) {
             int mlo, mhi;
-            if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid) - 1.f,
-                                (float)(Y0 + sy * p.grid) - 1.f, (float)(tile + 2),
-                                (float)(tile + 2), half_m, mlo, mhi)) {
+            if (!rx[sx + 1] || !ry[sy + 1]) continue;
+            if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid - M),
+                                (float)(Y0 + sy * p.grid - M), (float)(SP_T + 2 * M),
+                                (float)(SP_T + 2 * M), half_m, mlo, mhi)) {
               seg_info[lane * SEG_SLOTS + q] = th | ((sx + 1) << 16) | ((sy + 1) << 18);
               seg_mlo[lane * SEG_SLOTS + q] = mlo;
               seg_pre[lane * SEG_SLOTS + q] = mhi - mlo + 1;
@@ -408,69 +474,80 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
     }
     __syncthreads();
     const int total = seg_pre[NSEG];
+    SpreadCand cur;
+    fetch(lane, total, cur);
     for (int base = 0; base < total; base += 64) {
-      // stage the owned samples among the next 64 candidates
-      const int i = base + lane;
-      bool own = false;
-      int bxw = 0, byw = 0, th = 0, m = 0;
-      float X = 0.f, Y = 0.f;
-      if (i < total) {
-        int lo = 0, hi = NSEG;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (seg_pre[mid] <= i) lo = mid;
-          else hi = mid;
-        }
-        const int info = seg_info[lo];
-        th = info & 0xFFFF;
-        const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
-        m = seg_mlo[lo] + (i - seg_pre[lo]);
-        sample_pos(p.ncw, gcl, p.trig[th], m, X, Y);
-        // owned through this periodic copy only (copies may overlap when
-        // the tile spans the whole grid)
-        bxw = (int)floorf(X) - sx * p.grid - X0;
-        byw = (int)floorf(Y) - sy * p.grid - Y0;
-        own = bxw >= 0 && bxw < tile && byw >= 0 && byw < tile;
-      }
-      const unsigned long long mask = __ballot(own);
+      // stage the candidates whose taps reach the tile
+      const unsigned long long mask = __ballot(cur.use);
       const int cnt = __popcll(mask);
       const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                 __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-      if (own) {
+      if (cur.use) {
         float wx[W], wy[W];
-        gauss_taps<M>(X - floorf(X), p.beta, e2b, wx);
-        gauss_taps<M>(Y - floorf(Y), p.beta, e2b, wy);
+        gauss_taps<M>(cur.X - floorf(cur.X), p.beta, e2b, wx);
+        gauss_taps<M>(cur.Y - floorf(cur.Y), p.beta, e2b, wy);
 #pragma unroll
         for (int k = 0; k < W; ++k) {
-          st_wx[pos * W + k] = wx[k];
-          st_wy[pos * W + k] = wy[k];
+          if (PREC == 0) {
+            st_a[pos * W + k] = bf16_split(wy[k]);
+            st_b[pos * W + k] =
+                make_uint2(bf16_split(cur.c.x * wx[k]), bf16_split(cur.c.y * wx[k]));
+          } else if (PREC == 1) {
+            st_a[pos * W + k] = f16_bits(wy[k]);
+            st_b[pos * W + k] = make_uint2(f16_bits(cur.c.x * wx[k]), f16_bits(cur.c.y * wx[k]));
+          } else {
+            st_a[pos * W + k] = bf16_rne(wy[k]);
+            st_b[pos * W + k] = make_uint2(bf16_rne(cur.c.x * wx[k]), bf16_rne(cur.c.y * wx[k]));
+          }
         }
-        st_base[pos] = byw * P + bxw;
-        st_val[pos] = ld_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)),
-                           p.storage_dtype);
+        st_lx[pos] = cur.lx;
+        st_ly[pos] = cur.ly;
+      }
+      // padding samples of the last group contribute nothing
+      if (lane < SP_K) {
+        st_lx[cnt + lane] = -(1 << 20);
+        st_ly[cnt + lane] = -(1 << 20);
       }
       __syncthreads();
-      // every lane one tap; one sample per step
-      for (int s = 0; s < cnt; ++s) {
-        const int b = st_base[s];
-        const float2 v = st_val[s];
+      // the next batch's loads are in flight during the products below
+      fetch(base + 64 + lane, total, cur);
+      for (int g0 = 0; g0 < cnt; g0 += SP_K) {
+        v8u ah, al, brh, brl, bih, bil;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          if (toff[q] >= 0) {
-            const float w = st_wx[s * W + ti[q]] * st_wy[s * W + tj[q]];
-            float2 g = acc[b + toff[q]];
-            g.x = fmaf(v.x, w, g.x);
-            g.y = fmaf(v.y, w, g.y);
-            acc[b + toff[q]] = g;
-          }
+        for (int t = 0; t < 8; ++t) {
+          const int k = g0 + kq + t;
+          const int ia = r - st_ly[k];
+          const int ib = r - st_lx[k];
+          const unsigned a = (unsigned)ia < (unsigned)W ? st_a[k * W + ia] : 0u;
+          const uint2 b = (unsigned)ib < (unsigned)W ? st_b[k * W + ib] : make_uint2(0u, 0u);
+          ah[t] = (unsigned short)(a & 0xFFFFu);
+          al[t] = (unsigned short)(a >> 16);
+          brh[t] = (unsigned short)(b.x & 0xFFFFu);
+          brl[t] = (unsigned short)(b.x >> 16);
+          bih[t] = (unsigned short)(b.y & 0xFFFFu);
+          bil[t] = (unsigned short)(b.y >> 16);
+        }
+        cre = mfma16<PREC>(ah, brh, cre);
+        cim = mfma16<PREC>(ah, bih, cim);
+        if (PREC == 0) {
+          cre = mfma16<PREC>(ah, brl, cre);
+          cim = mfma16<PREC>(ah, bil, cim);
+          cre = mfma16<PREC>(al, brh, cre);
+          cim = mfma16<PREC>(al, bih, cim);
         }
       }
       __syncthreads();
     }
   }
-  __syncthreads();
-  float2* out = Gp + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * P * P;
-  for (int e = lane; e < P * P; e += 64) out[e] = acc[e];
+  // accumulator v of lane: tile row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
+  float2* g = G + (size_t)blockIdx.y * p.grid * p.grid;
+  const int kx = (X0 + r) & (p.grid - 1);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int row = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    const int ky = (Y0 + row) & (p.grid - 1);
+    g[(size_t)ky * p.grid + kx] = make_float2(cre[v], cim[v]);
+  }
 }
 
 // Forward USFFT step (3): interpolate slab (slab0 + blockIdx.y) of the grid
@@ -538,43 +615,20 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
 // Grid layout: G[slab_local][k2][k1], index k mod N_g.  After the row pass
 // the first n entries of each row hold x1 = ix - n/2 (ix < n).
 
-// Inverse FFT along x1 of the gridded slab.  The grid is assembled on load
-// from the padded spread tiles: cell u (unwrapped, u = k + N_g/2) of tile
-// u / T sits at padded index u % T + M - 1; the halos of the neighbouring
-// tiles (one period either way) add at u % T + M - 1 -+ T.
-__global__ __launch_bounds__(NT) void k_grid_rows_inv(KParams p, const float2* __restrict__ Gp,
-                                                      float2* __restrict__ G, int rows, int tile) {
+// Inverse FFT along x1 of each gridded slab row; the first n entries of
+// the row then hold x1 = ix - n/2.
+__global__ __launch_bounds__(NT) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
+                                                      int rows) {
   __shared__ float2 buf[2 * LDS_CPLX];
   const int N = p.grid;
-  const int P = tile + 2 * p.M - 1;
-  const int nt = N / tile;
   const int r0 = blockIdx.x * rows;
-  const float2* gp = Gp + (size_t)blockIdx.y * nt * nt * P * P;
+  float2* g = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < rows * N; e += NT) {
-    const int b = e / N, k1 = e - b * N;
-    const int r = r0 + b;
-    float2 sum = make_float2(0.f, 0.f);
-    if (r < N) {
-      const int u1 = (k1 + (N >> 1)) & (N - 1), u2 = (r + (N >> 1)) & (N - 1);
-      const int tx = u1 / tile, lx = u1 - tx * tile;
-      const int ty = u2 / tile, ly = u2 - ty * tile;
-      for (int sy = -1; sy <= 1; ++sy) {
-        const int py = ly + p.M - 1 + sy * tile;
-        if (py < 0 || py >= P) continue;
-        const int tyy = (ty - sy + nt) % nt;
-        for (int sx = -1; sx <= 1; ++sx) {
-          const int px = lx + p.M - 1 + sx * tile;
-          if (px < 0 || px >= P) continue;
-          const int txx = (tx - sx + nt) % nt;
-          sum = cadd(sum, gp[((size_t)(tyy * nt + txx) * P + py) * P + px]);
-        }
-      }
-    }
-    buf[e] = sum;
+    const int b = e / N;
+    buf[e] = (r0 + b < N) ? g[(size_t)(r0 + b) * N + (e - b * N)] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, true);
-  float2* g = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < rows * p.n; e += NT) {
     const int b = e / p.n, ix = e - b * p.n;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
@@ -768,10 +822,15 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 static int spread_tile(const KParams& p) { return p.grid <= 128 ? (p.grid < 32 ? p.grid : 32) : 64; }
 
 template <int M>
-static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns, int tile,
+static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns,
                           hipStream_t s) {
-  const int tiles = (kp.grid / tile) * (kp.grid / tile);
-  hipLaunchKernelGGL(k_spread<M>, dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0, tile);
+  const int tiles = (kp.grid / SP_T) * (kp.grid / SP_T);
+  if (kp.storage_dtype == LAMINO_F32)
+    hipLaunchKernelGGL((k_spread<M, 0>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
+  else if (kp.storage_dtype == LAMINO_F16)
+    hipLaunchKernelGGL((k_spread<M, 1>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
+  else
+    hipLaunchKernelGGL((k_spread<M, 2>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
 }
 template <int M>
 static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, int ns, int tile,
@@ -782,15 +841,14 @@ static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, i
 
 static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns,
                             hipStream_t s) {
-  const int tile = gridding_tile(kp.grid);
   switch (kp.M) {
-    case 2: launch_spread<2>(kp, D, G, s0, ns, tile, s); break;
-    case 3: launch_spread<3>(kp, D, G, s0, ns, tile, s); break;
-    case 4: launch_spread<4>(kp, D, G, s0, ns, tile, s); break;
-    case 5: launch_spread<5>(kp, D, G, s0, ns, tile, s); break;
-    case 6: launch_spread<6>(kp, D, G, s0, ns, tile, s); break;
-    case 7: launch_spread<7>(kp, D, G, s0, ns, tile, s); break;
-    default: launch_spread<8>(kp, D, G, s0, ns, tile, s); break;
+    case 2: launch_spread<2>(kp, D, G, s0, ns, s); break;
+    case 3: launch_spread<3>(kp, D, G, s0, ns, s); break;
+    case 4: launch_spread<4>(kp, D, G, s0, ns, s); break;
+    case 5: launch_spread<5>(kp, D, G, s0, ns, s); break;
+    case 6: launch_spread<6>(kp, D, G, s0, ns, s); break;
+    case 7: launch_spread<7>(kp, D, G, s0, ns, s); break;
+    default: launch_spread<8>(kp, D, G, s0, ns, s); break;
   }
 }
 static void interp_dispatch(const KParams& kp, const float2* G, void* D, int s0, int ns,
@@ -817,12 +875,12 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
   void* D = wptr(p, p->off_D);
   float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
-  float2* Gp = reinterpret_cast<float2*>(wptr(p, p->off_Gp));
   void* g = wptr(p, p->off_g);
   const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
   const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
+    StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
     hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp, d_data,
                        W1, t0, cp);
     hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
@@ -832,15 +890,20 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
   for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
-    spread_dispatch(kp, D, Gp, s0, ns, s);
-    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp,
-                       (const float2*)Gp, G, rows_g, gridding_tile(p->grid));
+    {
+      StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
+      spread_dispatch(kp, D, G, s0, ns, s);
+    }
+    StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
+    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp, G,
+                       rows_g);
     hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
                        (const float2*)G, g, s0, cols_g);
   }
   const int ncol = p->n * p->n;
   for (int z0 = 0; z0 < p->nz; z0 += p->z_chunk) {
     const int nzc = std::min(p->z_chunk, p->nz - z0);
+    StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
     hipLaunchKernelGGL(k_x3_adj, dim3(cdiv(ncol, XT), cdiv(nzc, XT)), dim3(NT), 0, s, kp,
                        (const void*)g, d_vol, z0, nzc);
   }
@@ -854,16 +917,23 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
   void* g = wptr(p, p->off_g);
   const int ncol = p->n * p->n;
-  hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, XT), cdiv(p->n_slab, XT)), dim3(NT), 0, s, kp,
-                     d_vol, g);
+  {
+    StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
+    hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, XT), cdiv(p->n_slab, XT)), dim3(NT), 0, s, kp,
+                       d_vol, g);
+  }
   const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
   const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
   for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
-    hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
-                       (const void*)g, G, s0, cols_g);
-    hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp, G,
-                       rows_g);
+    {
+      StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
+      hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
+                         (const void*)g, G, s0, cols_g);
+      hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp,
+                         G, rows_g);
+    }
+    StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
     interp_dispatch(kp, G, D, s0, ns, s);
   }
   const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
@@ -871,6 +941,7 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   const float scale = (float)(1.0 / ((double)p->h_p * p->w_p));
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
+    StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
     hipLaunchKernelGGL(k_proj_rows_inv, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
                        (const void*)D, W1, t0, rows_w);
     hipLaunchKernelGGL(k_proj_cols_inv, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp,

@@ -107,6 +107,14 @@ class Plan:
                         _stream_handle(stream))
         return out
 
+    def profile(self, enable=True):
+        """Record per-stage HIP events on the call stream for later calls."""
+        _abi.lamino_plan_profile(self._h, enable)
+
+    def stage_times(self, reset=False):
+        """{stage: (ms, launches)} accumulated while profiling was on."""
+        return _abi.lamino_plan_stage_times(self._h, reset)
+
     def spectra(self):
         """View of the stored spectra D[l][theta][k] of the last call (complex)."""
         i = self.info

@@ -1,0 +1,227 @@
+"""Continuous-batching FBP request server on one GPU.
+
+Requests (volume shape, angles, detector, tilt, device-resident data)
+arrive over time.  The server keeps a pool of execution slots; a slot owns
+a HIP stream (default priority) and a workspace sized for one shape class.
+A request is admitted as soon as a slot of its class is free or a new slot
+fits in the HBM budget; its FBP is enqueued on the slot's stream at once,
+so requests that arrive while others run overlap on the device.  Geometry
+tables depend on the tilt, so each request gets its own host plan (cheap:
+double-precision tables on the host) bound to the slot's cached device
+buffers; plans of repeated (shape, tilt) pairs are cached.  Completion is
+detected with an event per request; latency = completion - arrival.
+
+Every result is the same whether a request runs alone or in a mix: the
+operators are deterministic and a slot's workspace is private to it.
+"""
+import collections
+import ctypes
+import time
+
+import numpy as np
+import torch
+
+from . import _abi
+from .plan import Plan, _DTYPES, _FILTERS
+
+
+class Request:
+    __slots__ = ("rid", "shape", "tilt", "data", "arrival", "admitted", "done", "out", "event",
+                 "slot")
+
+    def __init__(self, rid, nz, n, n_theta, h, w, tilt, data, arrival=None):
+        self.rid = rid
+        self.shape = (nz, n, n_theta, h, w)
+        self.tilt = float(tilt)
+        self.data = data
+        self.arrival = time.perf_counter() if arrival is None else arrival
+        self.admitted = None
+        self.done = None
+        self.out = None
+        self.event = None
+        self.slot = None
+
+    @property
+    def voxels(self):
+        nz, n = self.shape[0], self.shape[1]
+        return nz * n * n
+
+
+class _Slot:
+    def __init__(self, key, plan, device):
+        self.key = key
+        self.proto = plan           # plan whose buffers this slot owns
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.busy = None
+        self.bytes = plan.tables.numel() + plan.work.numel()
+
+
+class Server:
+    """Admits FBP requests into per-class slots and runs them concurrently.
+
+    max_slots bounds the number of concurrently running requests;
+    hbm_budget bounds the bytes of all slot workspaces (0: no bound)."""
+
+    def __init__(self, max_slots=4, hbm_budget=0, storage_dtype="f16", data_dtype="f32",
+                 filter="shepp-logan", device=None, plan_cache=64):
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.max_slots = max_slots
+        self.hbm_budget = hbm_budget
+        self.storage_dtype = storage_dtype
+        self.data_dtype = data_dtype
+        self.filter = filter
+        self.slots = []
+        self.queue = collections.deque()
+        self.finished = []
+        self._plans = collections.OrderedDict()
+        self._plan_cache = plan_cache
+
+    # ------------------------------------------------------------ plans
+    def _class_key(self, req):
+        return req.shape
+
+    def _host_plan(self, req):
+        """C-ABI plan handle for (shape, tilt); cached (host memory only)."""
+        key = (req.shape, req.tilt)
+        h = self._plans.get(key)
+        if h is not None:
+            self._plans.move_to_end(key)
+            return h
+        nz, n, nt, hh, w = req.shape
+        g = _abi.lamino_geom()
+        g.nz, g.n, g.n_theta, g.h, g.w, g.tilt = nz, n, nt, hh, w, req.tilt
+        o = _abi.lamino_opts_default()
+        o.data_dtype = _DTYPES[self.data_dtype][0]
+        o.storage_dtype = _DTYPES[self.storage_dtype][0]
+        o.filter = _FILTERS[self.filter]
+        h = _abi.lamino_plan(g, o)
+        self._plans[key] = h
+        if len(self._plans) > self._plan_cache:
+            _, old = self._plans.popitem(last=False)
+            _abi.lamino_plan_destroy(old)
+        return h
+
+    def _footprint(self, req):
+        return sum(_abi.lamino_plan_sizes(self._host_plan(req)))
+
+    def _used_bytes(self):
+        return sum(s.bytes for s in self.slots)
+
+    # ------------------------------------------------------------ admission
+    def submit(self, req):
+        self.queue.append(req)
+        self._admit()
+
+    def _free_slot(self, req):
+        key = self._class_key(req)
+        for s in self.slots:
+            if s.busy is None and s.key == key:
+                return s
+        if len(self.slots) < self.max_slots or any(s.busy is None for s in self.slots):
+            need = self._footprint(req)
+            # evict idle slots of other classes until the new one fits
+            while (self.hbm_budget and self._used_bytes() + need > self.hbm_budget) or \
+                    len(self.slots) >= self.max_slots:
+                idle = [s for s in self.slots if s.busy is None and s.key != key]
+                if not idle:
+                    return None
+                self.slots.remove(idle[0])
+            if self.hbm_budget and need > self.hbm_budget:
+                raise ValueError(f"request {req.rid} needs {need} bytes, above the HBM budget")
+            nz, n, nt, h, w = req.shape
+            proto = Plan(nz, n, nt, h, w, req.tilt, data_dtype=self.data_dtype,
+                         storage_dtype=self.storage_dtype, filter=self.filter, device=self.device)
+            slot = _Slot(key, proto, self.device)
+            self.slots.append(slot)
+            return slot
+        return None
+
+    def _admit(self):
+        waiting = collections.deque()
+        while self.queue:
+            req = self.queue.popleft()
+            slot = self._free_slot(req)
+            if slot is None:
+                waiting.append(req)
+                continue
+            self._launch(slot, req)
+        self.queue = waiting
+
+    def _launch(self, slot, req):
+        h = self._host_plan(req)
+        proto = slot.proto
+        stream = slot.stream
+        # bind the request's tables into the slot's cached buffers on its stream
+        _abi.lamino_plan_bind(h, ctypes.c_void_p(proto.tables.data_ptr()),
+                              ctypes.c_void_p(proto.work.data_ptr()),
+                              ctypes.c_void_p(stream.cuda_stream))
+        nz, n = req.shape[0], req.shape[1]
+        with torch.cuda.stream(stream):
+            req.out = torch.empty((nz, n, n), dtype=torch.float32, device=self.device)
+        req.data.record_stream(stream)
+        _abi.lamino_fbp(h, ctypes.c_void_p(req.data.data_ptr()), ctypes.c_void_p(req.out.data_ptr()),
+                        ctypes.c_void_p(stream.cuda_stream))
+        req.event = torch.cuda.Event()
+        req.event.record(stream)
+        req.admitted = time.perf_counter()
+        req.slot = slot
+        slot.busy = req
+
+    # ------------------------------------------------------------ progress
+    def poll(self):
+        """Retire finished requests, admit waiting ones; returns #finished."""
+        n = 0
+        for s in self.slots:
+            r = s.busy
+            if r is not None and r.event.query():
+                r.done = time.perf_counter()
+                s.busy = None
+                self.finished.append(r)
+                n += 1
+        if n or self.queue:
+            self._admit()
+        return n
+
+    def drain(self):
+        while self.queue or any(s.busy is not None for s in self.slots):
+            if not self.poll():
+                time.sleep(2e-5)
+
+    def close(self):
+        self.drain()
+        for h in self._plans.values():
+            _abi.lamino_plan_destroy(h)
+        self._plans.clear()
+        self.slots.clear()
+
+    # ------------------------------------------------------------ metrics
+    def stats(self):
+        lat = np.array([r.done - r.arrival for r in self.finished]) * 1e3
+        if len(lat) == 0:
+            return {}
+        t0 = min(r.arrival for r in self.finished)
+        t1 = max(r.done for r in self.finished)
+        vox = sum(r.voxels for r in self.finished)
+        return {"requests": len(lat), "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "throughput_rps": len(lat) / (t1 - t0), "gvoxel_per_s": vox / (t1 - t0) / 1e9}
+
+
+def run_poisson(server, classes, rate, count, seed=0, tilt_range=(20.0, 40.0)):
+    """Submit `count` requests with Poisson arrivals at `rate` per second.
+
+    classes: list of (nz, n, n_theta, h, w, data_tensor); each request draws
+    a class uniformly and a tilt uniformly in tilt_range (degrees)."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    picks = rng.integers(0, len(classes), size=count)
+    tilts = np.deg2rad(rng.uniform(*tilt_range, size=count))
+    start = time.perf_counter()
+    arrivals = start + np.cumsum(gaps)
+    for i in range(count):
+        while time.perf_counter() < arrivals[i]:
+            server.poll()
+        nz, n, nt, h, w, data = classes[picks[i]]
+        server.submit(Request(i, nz, n, nt, h, w, tilts[i], data, arrival=float(arrivals[i])))
+    server.drain()
+    return server.stats()

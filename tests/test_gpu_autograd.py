@@ -1,0 +1,73 @@
+"""Autograd wrappers and CG least squares on the GPU (32^3 check instance)."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev, rel, to_dev, to_np
+from oracle import cg as ocg
+from oracle import nudft
+from oracle.geometry import Geometry
+from paper_2401_11101_amd import Plan
+from paper_2401_11101_amd.autograd import LaminoL, LaminoLstar, cgls
+
+pytestmark = pytest.mark.gpu
+
+
+def _instance(storage="f32", seed=0):
+    nz = n = h = 32
+    w = 40
+    nt = 48
+    phi = np.deg2rad(30)
+    plan = Plan(nz, n, nt, h, w, phi, storage_dtype=storage)
+    g = Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=phi)
+    rng = np.random.default_rng(seed)
+    return plan, g, rng
+
+
+@pytest.mark.parametrize("storage, tol", [("f32", 1e-3), ("bf16", 1e-2)])
+def test_gradient_matches_central_differences(storage, tol):
+    # 1/2 ||L mu - d||^2 is quadratic: the central difference is exact up
+    # to rounding, so it must equal <grad, v> from the autograd backward.
+    plan, g, rng = _instance(storage)
+    mu = to_dev(rng.standard_normal(plan.shape_vol)).requires_grad_(True)
+    d = to_dev(rng.standard_normal(plan.shape_data))
+    v = to_dev(rng.standard_normal(plan.shape_vol))
+    loss = 0.5 * torch.sum((LaminoL.apply(mu, plan).double() - d.double()) ** 2)
+    loss.backward()
+    gv = float(torch.sum(mu.grad.double() * v.double()))
+    eps = 1.0  # the loss is quadratic: any step is exact up to rounding
+    with torch.no_grad():
+        lp = 0.5 * torch.sum((plan.fwd(mu + eps * v).double() - d.double()) ** 2)
+        lm = 0.5 * torch.sum((plan.fwd(mu - eps * v).double() - d.double()) ** 2)
+    fd = float(lp - lm) / (2 * eps)
+    print(f"{storage}: <grad, v> {gv:.6e} central difference {fd:.6e}")
+    assert abs(gv - fd) <= tol * abs(fd)
+
+
+def test_adjoint_through_autograd():
+    plan, g, rng = _instance()
+    d = to_dev(rng.standard_normal(plan.shape_data)).requires_grad_(True)
+    v = to_dev(rng.standard_normal(plan.shape_vol))
+    out = torch.sum(LaminoLstar.apply(d, plan).double() * v.double())
+    out.backward()
+    # d/dd <L* d, v> = L v
+    assert rel(to_np(d.grad), to_np(plan.fwd(v))) < 1e-6
+    Lv = plan.fwd(v)
+    a = float(torch.sum(Lv.double() * d.detach().double()))
+    b = float(torch.sum(v.double() * plan.adj(d.detach()).double()))
+    assert abs(a - b) <= 1e-6 * float(Lv.double().norm() * d.detach().double().norm())
+
+
+def test_cgls_tracks_fp64_oracle_and_residual_decreases():
+    plan, g, rng = _instance()
+    f = rng.standard_normal(plan.shape_vol)
+    d = nudft.forward(f, g)
+    iters = 8
+    res = []
+    x = cgls(plan, to_dev(d), iters=iters, callback=lambda k, x, r: res.append(r))
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(res, res[1:]))
+    ref = ocg.cgls(lambda y: nudft.forward(y, g), lambda y: nudft.adjoint(y, g), d,
+                   np.zeros_like(f), iters)
+    e = rel(to_np(x), ref)
+    print(f"CGLS {iters} iterations vs FP64 oracle: rel-L2 {e:.2e}; residual {res[0]:.3e} -> {res[-1]:.3e}")
+    assert e < 1e-3

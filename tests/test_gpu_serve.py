@@ -1,0 +1,69 @@
+"""Continuous-batching server: completion, alone == in-mix, budgeted admission."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev
+from paper_2401_11101_amd import Plan
+from paper_2401_11101_amd.serve import Request, Server, run_poisson
+
+pytestmark = pytest.mark.gpu
+
+CLASSES = [(32, 32, 40, 32, 32), (24, 48, 60, 24, 48), (40, 40, 30, 40, 40)]
+
+
+def _data(shape, seed):
+    nz, n, nt, h, w = shape
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    return torch.randn((nt, h, w), generator=g).to(dev())
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_request_alone_equals_in_mix(storage):
+    shape = CLASSES[0]
+    tilt = np.deg2rad(27.0)
+    data = _data(shape, 0)
+    alone = Plan(*shape, tilt, storage_dtype=storage).fbp(data)
+    torch.cuda.synchronize()
+    srv = Server(max_slots=4, storage_dtype=storage)
+    reqs = []
+    for i in range(12):
+        cls = CLASSES[i % 3]
+        if i == 5:
+            r = Request(i, *shape, tilt, data)
+        else:
+            r = Request(i, *cls, np.deg2rad(20 + i), _data(cls, 100 + i))
+        reqs.append(r)
+        srv.submit(r)
+        srv.poll()
+    srv.drain()
+    assert len(srv.finished) == 12
+    mixed = reqs[5].out
+    torch.cuda.synchronize()
+    diff = float((mixed - alone).abs().max())
+    print(f"{storage}: max |in-mix - alone| = {diff:.3e}")
+    assert diff <= 1e-6 * float(alone.abs().max())
+    srv.close()
+
+
+def test_budget_limits_concurrency():
+    shape = CLASSES[1]
+    probe = Plan(*shape, 0.4, storage_dtype="f16")
+    one = probe.tables.numel() + probe.work.numel()
+    srv = Server(max_slots=4, hbm_budget=int(1.5 * one), storage_dtype="f16")
+    for i in range(6):
+        srv.submit(Request(i, *shape, 0.3 + 0.01 * i, _data(shape, i)))
+        assert sum(s.busy is not None for s in srv.slots) <= 1
+    srv.drain()
+    assert len(srv.finished) == 6
+    assert len(srv.slots) == 1
+    srv.close()
+
+
+def test_poisson_stream_reports_latency():
+    classes = [(*c, _data(c, j)) for j, c in enumerate(CLASSES)]
+    srv = Server(max_slots=3, storage_dtype="f16")
+    st = run_poisson(srv, classes, rate=200.0, count=40, seed=0)
+    print(st)
+    assert st["requests"] == 40 and st["p99_ms"] >= st["p50_ms"] > 0
+    srv.close()
