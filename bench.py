@@ -91,60 +91,135 @@ def algorithmic_work(info, storage_bytes, data_bytes):
     }
 
 
-def roofline(stages, work):
+def roofline(stages, work, steps):
+    """Dominant stage against its peak: algorithmic work per launch (work per
+    FBP / launches per FBP) over the mean launch duration from the events."""
     name = max(stages, key=lambda k: stages[k][0])
     ms, launches = stages[name]
     per_launch_ms = ms / max(launches, 1)
+    per_fbp = max(launches, 1) / steps
     w = work[name]
     if name == "gridding":
         # matrix-core gridding: algorithmic taps as float32 vector work
-        achieved = w["flops"] / max(launches, 1) / (per_launch_ms * 1e-3) / 1e12
+        achieved = w["flops"] / per_fbp / (per_launch_ms * 1e-3) / 1e12
         return {"kernel": "k_spread (gridding)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
-    achieved = w["bytes"] / max(launches, 1) / (per_launch_ms * 1e-3) / 1e9
+    achieved = w["bytes"] / per_fbp / (per_launch_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
 
 
-def cpu_baseline(data_np, proj=80, angles=100):
+def cpu_baseline(data_np, budget_s=15.0, max_slabs=64):
     """Oracle O3 (FP64 Gaussian USFFT FBP, numpy) on a bounded sample.
 
-    Times the oracle's detector transform + filter on `proj` projections and
-    the gridding / inverse FFT / psi correction / x3 accumulation of one
-    frequency slab restricted to `angles` angles, then scales both linearly
-    to the whole workload (all projections, all 2 h_p / 2 - 1 slabs)."""
+    Runs the oracle's detector transform + filter on all projections, then
+    grids / inverse-transforms / psi-corrects / x3-accumulates frequency
+    slabs (spread evenly over the spectrum, all angles) until `budget_s`
+    seconds have passed, and scales the mean slab time to all slabs the
+    oracle processes.  numpy's FFT, bincount and elementwise kernels run on
+    one thread; BLAS pools are held to one thread as well."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import filters, nudft, usfft
     from oracle.geometry import Geometry, freqs
 
-    g_sub = Geometry(nz=NZ, n=N, n_theta=proj, h=H, w=W, phi=TILT,
-                     theta=2 * np.pi * np.arange(proj) / NT)
-    t0 = time.perf_counter()
-    Gs = nudft.filter_spectra(nudft.data_spectra_fft(data_np[:proj], g_sub, half=True), g_sub,
-                              filters.SHEPP_LOGAN)
-    t_det = (time.perf_counter() - t0) * NT / proj
-    g_a = Geometry(nz=NZ, n=N, n_theta=angles, h=H, w=W, phi=TILT,
-                   theta=2 * np.pi * np.arange(angles) / NT)
-    N_g = usfft.default_grid(N)
-    ls_all = freqs(g_a.h_p)
-    l = g_a.h_p // 4
-    Ga = np.zeros((angles, len(freqs(g_a.w_p))), dtype=np.complex128)
-    Ga[:min(angles, proj)] = Gs[:min(angles, proj), l, :]
-    t0 = time.perf_counter()
-    X, Y = usfft.slab_positions(g_a, l, N_g)
-    gl = usfft.type1(Ga.reshape(-1), X, Y, N, N_g, 12)
-    E = nudft.x3_phases(g_a, +1.0)[:, int(np.where(ls_all == l)[0][0])]
-    acc = np.real(E[:, None, None] * gl[None])
-    t_slab = (time.perf_counter() - t0) * NT / angles
-    del acc
-    t_total = t_det + t_slab * len(ls_all)
-    measured = t_det * proj / NT + t_slab * angles / NT
-    return {"value": round(NZ * N * N / t_total / 1e9, 8), "unit": "GVoxel/s", "cores": 1,
+    g = Geometry(nz=NZ, n=N, n_theta=NT, h=H, w=W, phi=TILT)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        Gs = nudft.filter_spectra(nudft.data_spectra_fft(data_np, g, half=True), g,
+                                  filters.SHEPP_LOGAN)
+        t_det = time.perf_counter() - t0
+        N_g = usfft.default_grid(N)
+        ls_all = freqs(g.h_p)
+        E_all = nudft.x3_phases(g, +1.0)
+        half = g.h_p // 2
+        order = [(k * 97) % half for k in range(half)]
+        t_slabs, done = 0.0, 0
+        for l in order[:max_slabs]:
+            t1 = time.perf_counter()
+            X, Y = usfft.slab_positions(g, l, N_g)
+            gl = usfft.type1(Gs[:, l, :].reshape(-1), X, Y, N, N_g, 12)
+            E = E_all[:, int(np.where(ls_all == l)[0][0])]
+            acc = np.real(E[:, None, None] * gl[None])
+            del acc
+            t_slabs += time.perf_counter() - t1
+            done += 1
+            if t_det + t_slabs >= budget_s:
+                break
+    t_total = t_det + t_slabs / done * len(ls_all)
+    return {"value": round(NZ * N * N / t_total / 1e9, 9), "unit": "GVoxel/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"O3 FP64 Gaussian-USFFT FBP (numpy, M=12, single thread): detector FFT + "
-                      f"filter of {proj}/{NT} projections and one of {len(ls_all)} frequency slabs "
-                      f"gridded from {angles}/{NT} angles, scaled linearly to the whole 256^3 FBP "
-                      f"({measured:.1f} s measured, {t_total:.0f} s extrapolated)"}
+            "sample": f"O3 FP64 Gaussian-USFFT FBP (numpy, M=12, one thread): detector FFT + "
+                      f"filter of all {NT} projections and {done} of the {len(ls_all)} frequency "
+                      f"slabs the oracle grids (all angles), scaled linearly to the whole 256^3 FBP "
+                      f"({t_det + t_slabs:.1f} s measured, {t_total:.0f} s extrapolated)"}
+
+
+def serving(dev, count, rate=20.0):
+    """Poisson stream of fp16-gridded FBP requests over three size classes."""
+    from paper_2401_11101_amd.serve import Server, run_poisson
+
+    classes = []
+    for (nz, n, nt), seed in zip([(128, 128, 180), (256, 256, 400), (256, 512, 720)], (10, 11, 12)):
+        h, w = nz, n  # detector rows x columns = nz x n for every class
+        ells = synth.random_ellipsoids(30, nz, n, seed=seed)
+        d = synth.project_ellipsoids(ells, nt, h, w, np.deg2rad(30.0), device=dev, dtype=torch.float32)
+        d = synth.add_noise(d, 0.005, seed=seed + 100).contiguous()
+        classes.append((nz, n, nt, h, w, d))
+    srv = Server(max_slots=4, hbm_budget=32 << 30, storage_dtype="f16", data_dtype="f32", device=dev)
+    # warm every class once (plans, slots, kernels), then the timed stream
+    run_poisson(srv, classes, rate=1000.0, count=6, seed=99)
+    srv.finished.clear()
+    st = run_poisson(srv, classes, rate=rate, count=count, seed=0)
+    srv.close()
+    return {"requests": st["requests"], "rate_per_s": rate, "p50_ms": round(st["p50_ms"], 3),
+            "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
+            "throughput_rps": round(st["throughput_rps"], 3), "gvoxel_per_s": round(st["gvoxel_per_s"], 4),
+            "classes": "U{128^3/180, 256^3/400, 512x512x256/720}, tilt U[20,40] deg, fp16 storage, "
+                       "4 slots, data resident on the device"}
+
+
+def large_volume(dev, steps):
+    """1024 x 1024 x 512 volume, 1500 projections 512 x 1024, tilt 20 deg, fp16 data
+    and storage, x3 output in z-chunks of 64."""
+    from paper_2401_11101_amd import Plan
+
+    nz, n, nt, h, w = 512, 1024, 1500, 512, 1024
+    ells = synth.random_ellipsoids(20, nz, n, seed=0)
+    d = synth.project_ellipsoids(ells, nt, h, w, np.deg2rad(20.0), device=dev, dtype=torch.float32,
+                                 theta_chunk=8)
+    d = synth.apply_speckle(d, 0.1, seed=1).half().contiguous()
+    plan = Plan(nz, n, nt, h, w, np.deg2rad(20.0), data_dtype="f16", storage_dtype="f16", z_chunk=64)
+    vol = torch.empty((nz, n, n), dtype=torch.float32, device=dev)
+    ms, _, st = time_op(lambda: plan.fbp(d, out=vol), steps, 1, torch.cuda.current_stream(), plan)
+    return {"workload": "FBP 1024x1024x512 from 1500 projections 512x1024, tilt 20 deg, fp16 data "
+                        "and storage, z-chunks of 64", "ms_per_step": round(ms, 3),
+            "gvoxel_per_s": round(nz * n * n / (ms * 1e-3) / 1e9, 4),
+            "stages_ms_per_step": {k: round(v[0] / steps, 3) for k, v in st.items()},
+            "workspace_gb": round(plan.work.numel() / 2**30, 3)}
+
+
+def cg_reconstruction(dev, iters=20):
+    """CGLS, 20 iterations: 256^3 volume, 720 projections 256 x 320, tilt 30 deg, bf16 storage."""
+    from paper_2401_11101_amd import Plan
+    from paper_2401_11101_amd.autograd import cgls
+
+    nz = n = h = 256
+    w, nt = 320, 720
+    ells = synth.random_ellipsoids(50, nz, n, seed=0)
+    d = synth.project_ellipsoids(ells, nt, h, w, np.deg2rad(30.0), device=dev, dtype=torch.float32)
+    plan = Plan(nz, n, nt, h, w, np.deg2rad(30.0), storage_dtype="bf16")
+    res = []
+    cgls(plan, d, iters=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cgls(plan, d, iters=iters, callback=lambda k, x, r: res.append(r))
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    return {"workload": "CGLS 20 iterations, 256^3 volume, 720 projections 256x320, tilt 30 deg, "
+                        "bf16 storage", "seconds": round(t, 3), "ms_per_iteration": round(t * 1e3 / iters, 3),
+            "residual_first_last": [round(res[0], 4), round(res[-1], 4)]}
 
 
 def main():
@@ -153,7 +228,21 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving stream (0 skips it)")
+    ap.add_argument("--extra", action="store_true",
+                    help="also time the 1024^2 x 512 volume and the CGLS reconstruction")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (scale for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 1 << 30, "copies": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(DESIGN.md describes how it would shard)", file=sys.stderr)
@@ -208,8 +297,16 @@ def main():
             "fwd_f32": {k: round(v[0] / max(3, args.steps // 2), 4) for k, v in st_fwd.items()},
         },
         "wall_ms_per_step": {"f32": round(wall32, 4), "f16": round(wall16, 4)},
-        "roofline": roofline(st32, work),
+        "roofline": roofline(st32, work, args.steps),
     }
+    if args.serve_requests:
+        log(f"serving: {args.serve_requests} Poisson requests at 20/s")
+        line["serving"] = serving(dev, args.serve_requests)
+    if args.extra:
+        log("timing the 1024^2 x 512 volume")
+        line["large_volume"] = large_volume(dev, 3)
+        log("timing CGLS")
+        line["cgls"] = cg_reconstruction(dev)
     if not args.no_cpu:
         log("timing the CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(data.double().cpu().numpy())

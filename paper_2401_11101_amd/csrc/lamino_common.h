@@ -32,29 +32,29 @@ LAM_HD int ilog2(int n) {
 }
 
 // ------------------------------------------------------------ FFT passes
-// Stockham autosort FFT of length N = 2^log2N, radix 4 passes followed by
-// one radix-2 pass when log2N is odd.  A pass with sub-transform size Ns
-// maps butterfly j (0 <= j < N/R) from positions j + r N/R to positions
-// (j - j%Ns) R + j%Ns + r Ns after twiddling by w^(r (j%Ns)),
-// w = exp(-+2 pi i / (Ns R)).  The twiddle table holds
+// Stockham autosort FFT of length N = 2^log2N: radix-8 passes, then one
+// radix-4 or radix-2 pass for the remaining bits.  A pass with sub-transform
+// size Ns maps butterfly j (0 <= j < N/R) from positions j + r N/R to
+// positions (j - j%Ns) R + j%Ns + q Ns after twiddling input r by
+// w^(r (j%Ns)), w = exp(-+2 pi i / (Ns R)).  The twiddle table holds
 // tw[t] = exp(-2 pi i t / Nmax), Nmax = 2^log2max >= N.
 
 struct FftPass {
-  int radix;   // 4 or 2
+  int radix;   // 8, 4 or 2
   int log2Ns;  // log2 of the sub-transform size before this pass
 };
 
-LAM_HD int fft_num_passes(int log2N) { return (log2N >> 1) + (log2N & 1); }
+LAM_HD int fft_num_passes(int log2N) { return log2N / 3 + (log2N % 3 ? 1 : 0); }
 
 LAM_HD FftPass fft_pass(int log2N, int p) {
   FftPass f;
-  const int n4 = log2N >> 1;
-  if (p < n4) {
-    f.radix = 4;
-    f.log2Ns = 2 * p;
+  const int n8 = log2N / 3;
+  if (p < n8) {
+    f.radix = 8;
+    f.log2Ns = 3 * p;
   } else {
-    f.radix = 2;
-    f.log2Ns = 2 * n4;
+    f.radix = (log2N % 3 == 2) ? 4 : 2;
+    f.log2Ns = 3 * n8;
   }
   return f;
 }
@@ -91,6 +91,54 @@ LAM_HD void r4_compute_store(float2* a, int j, int log2Ns, const float2* tw, int
   a[o + Ns] = cadd(d02, rot);
   a[o + 2 * Ns] = csub(s02, s13);
   a[o + 3 * Ns] = csub(d02, rot);
+}
+
+LAM_HD void r8_load(const float2* a, int N, int j, float2 v[8]) {
+  const int q = N >> 3;
+  for (int r = 0; r < 8; ++r) v[r] = a[j + r * q];
+}
+
+// 4-point DFT in place (forward: exp(-2 pi i rq/4); inverse: conjugate).
+LAM_HD void dft4(float2& x0, float2& x1, float2& x2, float2& x3, bool inv) {
+  const float2 s02 = cadd(x0, x2), d02 = csub(x0, x2);
+  const float2 s13 = cadd(x1, x3), d13 = csub(x1, x3);
+  const float2 rot = inv ? mul_pi(d13) : mul_mi(d13);
+  x0 = cadd(s02, s13);
+  x2 = csub(s02, s13);
+  x1 = cadd(d02, rot);
+  x3 = csub(d02, rot);
+}
+
+LAM_HD void r8_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[8]) {
+  const int Ns = 1 << log2Ns;
+  const int k = j & (Ns - 1);
+  if (Ns > 1) {
+    const int sh = log2max - (log2Ns + 3);
+    for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twiddle(tw, (r * k) << sh, inv));
+  }
+  // 8-point DFT: 4-point DFTs of the even and odd inputs, then combine with
+  // w8^q, w8 = exp(-+2 pi i / 8)
+  float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3, inv);
+  dft4(o0, o1, o2, o3, inv);
+  const float h = 0.70710678118654752f;
+  // o1 *= w8, o2 *= w8^2, o3 *= w8^3
+  o1 = inv ? make_float2(h * (o1.x - o1.y), h * (o1.x + o1.y))
+           : make_float2(h * (o1.x + o1.y), h * (o1.y - o1.x));
+  o2 = inv ? mul_pi(o2) : mul_mi(o2);
+  o3 = inv ? make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y))
+           : make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
+  const int o = ((j - k) << 3) + k;
+  a[o] = cadd(e0, o0);
+  a[o + Ns] = cadd(e1, o1);
+  a[o + 2 * Ns] = cadd(e2, o2);
+  a[o + 3 * Ns] = cadd(e3, o3);
+  a[o + 4 * Ns] = csub(e0, o0);
+  a[o + 5 * Ns] = csub(e1, o1);
+  a[o + 6 * Ns] = csub(e2, o2);
+  a[o + 7 * Ns] = csub(e3, o3);
 }
 
 LAM_HD void r2_load(const float2* a, int N, int j, float2 v[2]) {

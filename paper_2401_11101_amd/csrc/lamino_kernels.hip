@@ -13,7 +13,7 @@
 // Forward projection (eq:fftfwd) runs the transposes in reverse order:
 //   x3_fwd, grid_cols_fwd, grid_rows_fwd, interp, proj_rows_inv, proj_cols_inv.
 //
-// FFTs are Stockham radix-4/2 passes over LDS with twiddles from a table
+// FFTs are Stockham radix-8/4/2 passes over LDS with twiddles from a table
 // computed in double precision on the host.  All arithmetic is float32;
 // stored spectra and slab planes may be float16 / bfloat16.
 #include "lamino_common.h"
@@ -21,7 +21,8 @@
 
 namespace lam {
 
-constexpr int NT = 256;        // threads per block
+constexpr int NT = 256;        // threads per block (x3 transform, interpolation)
+constexpr int NTF = 512;       // threads per block of the FFT kernels
 constexpr int LDS_CPLX = 4096; // complex values per FFT block buffer (two buffers: 64 KB)
 constexpr int TILE_MAX = 64;   // gridding tile edge
 constexpr int SEG_THETA = 128; // angles per candidate pass
@@ -59,10 +60,19 @@ __device__ float2* block_fft(float2* a, float2* b, int log2N, int B,
   const int np = fft_num_passes(log2N);
   for (int p = 0; p < np; ++p) {
     const FftPass f = fft_pass(log2N, p);
-    if (f.radix == 4) {
+    if (f.radix == 8) {
+      const int per = N >> 3;
+      const int total = B * per;
+      for (int t = threadIdx.x; t < total; t += NTF) {
+        const int bb = t >> (log2N - 3), j = t & (per - 1);
+        float2 v[8];
+        r8_load(a + bb * N, N, j, v);
+        r8_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
+      }
+    } else if (f.radix == 4) {
       const int per = N >> 2;
       const int total = B * per;
-      for (int t = threadIdx.x; t < total; t += NT) {
+      for (int t = threadIdx.x; t < total; t += NTF) {
         const int bb = t >> (log2N - 2), j = t & (per - 1);
         float2 v[4];
         r4_load(a + bb * N, N, j, v);
@@ -71,7 +81,7 @@ __device__ float2* block_fft(float2* a, float2* b, int log2N, int B,
     } else {
       const int per = N >> 1;
       const int total = B * per;
-      for (int t = threadIdx.x; t < total; t += NT) {
+      for (int t = threadIdx.x; t < total; t += NTF) {
         const int bb = t >> (log2N - 1), j = t & (per - 1);
         float2 v[2];
         r2_load(a + bb * N, N, j, v);
@@ -87,7 +97,7 @@ __device__ float2* block_fft(float2* a, float2* b, int log2N, int B,
 }
 
 __device__ __forceinline__ void lds_zero(float2* buf, int count) {
-  for (int e = threadIdx.x; e < count; e += NT) buf[e] = make_float2(0.f, 0.f);
+  for (int e = threadIdx.x; e < count; e += NTF) buf[e] = make_float2(0.f, 0.f);
 }
 
 // ====================================================== detector transforms
@@ -96,7 +106,7 @@ __device__ __forceinline__ void lds_zero(float2* buf, int count) {
 // Column pairs (c, c+1) of projection theta0 + blockIdx.y packed as one
 // complex h_p-point FFT along v; the two real spectra are separated by
 // Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
-__global__ __launch_bounds__(NT) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
+__global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
                                                       int cp) {
   __shared__ float2 buf[2 * LDS_CPLX];
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(NT) void k_proj_cols_fwd(KParams p, const void* __r
   __syncthreads();
   const int wide = 2 * cp;
   float* bf = reinterpret_cast<float*>(buf);
-  for (int e = threadIdx.x; e < p.h * wide; e += NT) {
+  for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
     const int r = e / wide, cl = e - r * wide;
     const int c = c0 + cl;
     const float v = c < p.w ? ld_r(data, ((size_t)th * p.h + r) * p.w + c, p.data_dtype) : 0.f;
@@ -118,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_proj_cols_fwd(KParams p, const void* __r
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, false);
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < p.n_slab * wide; e += NT) {
+  for (int e = threadIdx.x; e < p.n_slab * wide; e += NTF) {
     const int l = e / wide, cl = e - l * wide;
     const int c = c0 + cl;
     if (c >= p.w) continue;
@@ -133,7 +143,7 @@ __global__ __launch_bounds__(NT) void k_proj_cols_fwd(KParams p, const void* __r
 
 // Rows l of the column spectra: w_p-point FFT along u, times the transfer
 // function, stored as D[l][theta][k] (k = m mod w_p).
-__global__ __launch_bounds__(NT) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
+__global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
                                                       int theta0, int rows) {
   __shared__ float2 buf[2 * LDS_CPLX];
@@ -144,14 +154,14 @@ __global__ __launch_bounds__(NT) void k_proj_rows_fwd(KParams p, const float2* _
   lds_zero(buf, rows * wp);
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < rows * p.w; e += NT) {
+  for (int e = threadIdx.x; e < rows * p.w; e += NTF) {
     const int b = e / p.w, c = e - b * p.w;
     const int l = l0 + b;
     if (l < p.n_slab) buf[b * wp + ((c - p.w / 2) & (wp - 1))] = w1[base + (size_t)l * p.w + c];
   }
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, false);
-  for (int e = threadIdx.x; e < rows * wp; e += NT) {
+  for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e / wp, k = e - b * wp;
     const int l = l0 + b;
     if (l < p.n_slab)
@@ -161,7 +171,7 @@ __global__ __launch_bounds__(NT) void k_proj_rows_fwd(KParams p, const float2* _
 
 // Inverse of the row step (forward projection): D[l][theta][.] -> inverse
 // FFT along m -> detector columns, W1[theta_local][l][c].
-__global__ __launch_bounds__(NT) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
+__global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
                                                       float2* __restrict__ w1, int theta0,
                                                       int rows) {
   __shared__ float2 buf[2 * LDS_CPLX];
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(NT) void k_proj_rows_inv(KParams p, const void* __r
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
   const int wp = p.w_p;
-  for (int e = threadIdx.x; e < rows * wp; e += NT) {
+  for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e / wp, k = e - b * wp;
     const int l = l0 + b;
     float2 v = make_float2(0.f, 0.f);
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_proj_rows_inv(KParams p, const void* __r
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, true);
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < rows * p.w; e += NT) {
+  for (int e = threadIdx.x; e < rows * p.w; e += NTF) {
     const int b = e / p.w, c = e - b * p.w;
     const int l = l0 + b;
     if (l < p.n_slab) w1[base + (size_t)l * p.w + c] = res[b * wp + ((c - p.w / 2) & (wp - 1))];
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(NT) void k_proj_rows_inv(KParams p, const void* __r
 // l = 0 dropped), packed as Z = X_c + i X_{c+1}, inverse transformed along
 // v, and the real / imaginary parts scaled by 1/(h_p w_p) give the two
 // detector columns.
-__global__ __launch_bounds__(NT) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
+__global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ data, int theta0,
                                                       int cp, float scale) {
   __shared__ float2 buf[2 * LDS_CPLX];
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(NT) void k_proj_cols_inv(KParams p, const float2* _
   lds_zero(buf, cp * hp);
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < p.n_slab * cp; e += NT) {
+  for (int e = threadIdx.x; e < p.n_slab * cp; e += NTF) {
     const int l = e / cp, pp = e - l * cp;
     const int ca = c0 + 2 * pp, cb = ca + 1;
     const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
@@ -220,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_proj_cols_inv(KParams p, const float2* _
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, true);
   const int wide = 2 * cp;
   const float* bf = reinterpret_cast<const float*>(res);
-  for (int e = threadIdx.x; e < p.h * wide; e += NT) {
+  for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
     const int r = e / wide, cl = e - r * wide;
     const int c = c0 + cl;
     if (c >= p.w) continue;
@@ -617,38 +627,38 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
 
 // Inverse FFT along x1 of each gridded slab row; the first n entries of
 // the row then hold x1 = ix - n/2.
-__global__ __launch_bounds__(NT) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
+__global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
                                                       int rows) {
   __shared__ float2 buf[2 * LDS_CPLX];
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
-  for (int e = threadIdx.x; e < rows * N; e += NT) {
+  for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e / N;
     buf[e] = (r0 + b < N) ? g[(size_t)(r0 + b) * N + (e - b * N)] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, true);
-  for (int e = threadIdx.x; e < rows * p.n; e += NT) {
+  for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
     const int b = e / p.n, ix = e - b * p.n;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
   }
 }
 
-__global__ __launch_bounds__(NT) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
+__global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
                                                       void* __restrict__ g, int slab0, int cols) {
   __shared__ float2 buf[2 * LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float2* gg = G + (size_t)blockIdx.y * N * N;
-  for (int e = threadIdx.x; e < cols * N; e += NT) {
+  for (int e = threadIdx.x; e < cols * N; e += NTF) {
     const int k2 = e / cols, c = e - k2 * cols;
     buf[c * N + k2] = (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, true);
   const int l = slab0 + blockIdx.y;
-  for (int e = threadIdx.x; e < cols * p.n; e += NT) {
+  for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
     const int y = e / cols, c = e - y * cols;
     const int ix = ix0 + c;
     if (ix >= p.n) continue;
@@ -657,7 +667,7 @@ __global__ __launch_bounds__(NT) void k_grid_cols_adj(KParams p, const float2* _
   }
 }
 
-__global__ __launch_bounds__(NT) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
+__global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
   __shared__ float2 buf[2 * LDS_CPLX];
   const int N = p.grid;
@@ -665,7 +675,7 @@ __global__ __launch_bounds__(NT) void k_grid_cols_fwd(KParams p, const void* __r
   const int l = slab0 + blockIdx.y;
   lds_zero(buf, cols * N);
   __syncthreads();
-  for (int e = threadIdx.x; e < cols * p.n; e += NT) {
+  for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
     const int y = e / cols, c = e - y * cols;
     const int ix = ix0 + c;
     if (ix >= p.n) continue;
@@ -675,13 +685,13 @@ __global__ __launch_bounds__(NT) void k_grid_cols_fwd(KParams p, const void* __r
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, false);
   float2* gg = G + (size_t)blockIdx.y * N * N;
-  for (int e = threadIdx.x; e < cols * N; e += NT) {
+  for (int e = threadIdx.x; e < cols * N; e += NTF) {
     const int k2 = e / cols, c = e - k2 * cols;
     if (ix0 + c < p.n) gg[(size_t)k2 * N + ix0 + c] = res[c * N + k2];
   }
 }
 
-__global__ __launch_bounds__(NT) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
+__global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
                                                       int rows) {
   __shared__ float2 buf[2 * LDS_CPLX];
   const int N = p.grid;
@@ -689,13 +699,13 @@ __global__ __launch_bounds__(NT) void k_grid_rows_fwd(KParams p, float2* __restr
   float2* g = G + (size_t)blockIdx.y * N * N;
   lds_zero(buf, rows * N);
   __syncthreads();
-  for (int e = threadIdx.x; e < rows * p.n; e += NT) {
+  for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
     const int b = e / p.n, ix = e - b * p.n;
     if (r0 + b < N) buf[b * N + ((ix - p.n / 2) & (N - 1))] = g[(size_t)(r0 + b) * N + ix];
   }
   __syncthreads();
   const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, false);
-  for (int e = threadIdx.x; e < rows * N; e += NT) {
+  for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e / N;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + (e - b * N)] = res[e];
   }
@@ -881,9 +891,9 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
-    hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp, d_data,
+    hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp, d_data,
                        W1, t0, cp);
-    hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
+    hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
                        (const float2*)W1, D, kp.filt, t0, rows_w);
   }
   const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
@@ -895,9 +905,9 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
       spread_dispatch(kp, D, G, s0, ns, s);
     }
     StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
-    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp, G,
+    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp, G,
                        rows_g);
-    hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
+    hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
                        (const float2*)G, g, s0, cols_g);
   }
   const int ncol = p->n * p->n;
@@ -928,9 +938,9 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
-      hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NT), 0, s, kp,
+      hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
                          (const void*)g, G, s0, cols_g);
-      hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NT), 0, s, kp,
+      hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp,
                          G, rows_g);
     }
     StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
@@ -942,9 +952,9 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
-    hipLaunchKernelGGL(k_proj_rows_inv, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NT), 0, s, kp,
+    hipLaunchKernelGGL(k_proj_rows_inv, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
                        (const void*)D, W1, t0, rows_w);
-    hipLaunchKernelGGL(k_proj_cols_inv, dim3(cdiv(p->w, 2 * cp), nt), dim3(NT), 0, s, kp,
+    hipLaunchKernelGGL(k_proj_cols_inv, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp,
                        (const float2*)W1, d_data, t0, cp, scale);
   }
   return hipGetLastError();

@@ -1,6 +1,6 @@
 // Host-only checks of the index logic the kernels share (no GPU needed).
 //
-//  fft     Stockham radix-4/2 passes of lamino_common.h, run serially over
+//  fft     Stockham radix-8/4/2 passes of lamino_common.h, run serially over
 //          ping-pong buffers, against a naive double-precision DFT for
 //          N = 2 .. 4096, both directions.
 //  cand    for random slabs, angles and tiles: every sample whose Gaussian
@@ -40,7 +40,11 @@ static int check_fft() {
       for (int p = 0; p < fft_num_passes(log2N); ++p) {
         const FftPass f = fft_pass(log2N, p);
         for (int j = 0; j < N / f.radix; ++j) {
-          if (f.radix == 4) {
+          if (f.radix == 8) {
+            float2 v[8];
+            r8_load(src, N, j, v);
+            r8_compute_store(dst, j, f.log2Ns, tw.data(), log2max, inv, v);
+          } else if (f.radix == 4) {
             float2 v[4];
             r4_load(src, N, j, v);
             r4_compute_store(dst, j, f.log2Ns, tw.data(), log2max, inv, v);

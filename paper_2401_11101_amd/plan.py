@@ -67,8 +67,11 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _abi.lamino_plan_destroy(h)
+        if h and _abi is not None and _abi.lamino_plan_destroy is not None:
+            try:
+                _abi.lamino_plan_destroy(h)
+            except Exception:  # interpreter shutdown: module state may be gone
+                pass
             self._h = None
 
     # ---------------------------------------------------------------- checks
