@@ -222,6 +222,29 @@ def cg_reconstruction(dev, iters=20):
             "residual_first_last": [round(res[0], 4), round(res[-1], 4)]}
 
 
+def copy_calibration(nbytes=1 << 30):
+    """Plain copies of `nbytes` with 4-, 8- and 16-byte lane accesses (and the
+    runtime's own device copy), each once: under rocprofv3 --pmc their
+    FETCH_SIZE / WRITE_SIZE give the counters' scale for known traffic."""
+    import ctypes
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2401_11101_amd", "lib", "libcopycalib.so"))
+    lib.lamino_calib_copy.restype = ctypes.c_int
+    lib.lamino_calib_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_int, ctypes.c_void_p]
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    s = torch.cuda.current_stream()
+    for width in (4, 8, 16):
+        rc = lib.lamino_calib_copy(x.data_ptr(), y.data_ptr(), nbytes, width, s.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"lamino_calib_copy width {width}: {rc}")
+    y.copy_(x)
+    torch.cuda.synchronize()
+    assert bool((y == 1).all())
+    print(json.dumps({"copy_bytes_each_way": nbytes, "widths": [4, 8, 16, "runtime"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,15 +256,10 @@ def main():
     ap.add_argument("--extra", action="store_true",
                     help="also time the 1024^2 x 512 volume and the CGLS reconstruction")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device-to-device copy (scale for HBM counters)")
+                    help="only run 1 GiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.copy_calibration:
-        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": 1 << 30, "copies": 3}), flush=True)
+        copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -1,4 +1,6 @@
-"""Build the gfx950 shared library `lib/liblamino.so` in-tree with hipcc.
+"""Build the gfx950 shared library `lib/liblamino.so` in-tree with hipcc
+(plus `lib/libcopycalib.so`, the counter-calibration copies, and the
+host self-test of the kernels' index logic).
 
 Usage: python -m paper_2401_11101_amd.build  (or call build()).
 """
@@ -12,6 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "liblamino.so")
 SELFTEST = os.path.join(LIBDIR, "lamino_selftest_host")
+CALIB = os.path.join(LIBDIR, "libcopycalib.so")
 
 SOURCES = ["lamino_api.cpp", "lamino_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -36,6 +39,13 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # copy kernels that calibrate the HBM byte counters (measurement only)
+    tmp = CALIB + ".tmp"
+    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, "copy_calib.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, CALIB)
     # host-only checks of the kernels' index logic
     tmp = SELFTEST + ".tmp"
     cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),

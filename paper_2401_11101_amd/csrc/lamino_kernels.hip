@@ -16,6 +16,8 @@
 // FFTs are Stockham radix-8/4/2 passes over LDS with twiddles from a table
 // computed in double precision on the host.  All arithmetic is float32;
 // stored spectra and slab planes may be float16 / bfloat16.
+#include <type_traits>
+
 #include "lamino_common.h"
 #include "lamino_internal.h"
 
@@ -317,8 +319,8 @@ __device__ __forceinline__ int find_segment(const SegLists& S, int i) {
 template <int M>
 __device__ __forceinline__ void gauss_taps(float f, float beta, float e2b, float w[2 * M]) {
   const float d0 = (float)(1 - M) - f;
-  w[0] = expf(-beta * d0 * d0);
-  float r = expf(-beta * (2.f * d0 + 1.f));
+  w[0] = __expf(-beta * d0 * d0);
+  float r = __expf(-beta * (2.f * d0 + 1.f));
 #pragma unroll
   for (int i = 1; i < 2 * M; ++i) {
     w[i] = w[i - 1] * r;
@@ -331,33 +333,48 @@ __device__ __forceinline__ void gauss_taps(float f, float beta, float e2b, float
 //     G_tile += wy_s (c_s wx_s)^T,
 // wy_s / wx_s the sample's Gaussian weights on the tile rows / columns (zero
 // outside its 2M taps), so a batch of K samples is one 32 x 32 x K matrix
-// product with the tile held in MFMA accumulators.  One wave per tile; it
-// visits every sample whose taps reach the tile (any periodic copy), stages
-// up to 64 of them in LDS, and feeds them 16 at a time.  Float32 storage
-// uses bf16 hi/lo splits (three products per component, ~2^-17 relative
-// error); float16 / bfloat16 storage uses one float16 / bfloat16 product.
+// product with the tile held in MFMA accumulators.  One wave per tile.
+//
+// Candidates: for each periodic copy of the tile that the slab's samples can
+// reach and each pass of 64 angles, lane j finds the m-interval of angle j
+// whose Gaussian footprint meets the copy (an exact line / box intersection);
+// the non-empty intervals are compacted with a ballot and held one per lane
+// (start, first m, angle), and a batch of 64 consecutive candidates locates
+// its intervals by a uniform scan over the few interval starts it spans.
+//
+// Staging: each candidate stores its 2M row weights and 2M column values
+// (c times the column weights) in an LDS slot framed by a zero entry on each
+// side.  Lane r of the matrix operand needs the tap r - ly of a sample whose
+// taps start at tile row ly; the byte offset of that tap is clamped onto the
+// slot's zeros, so rows outside the footprint read 0 with no branch.
+//
+// Precision: float32 storage uses bf16 hi / lo splits (three products per
+// component, ~2^-17 relative error); float16 / bfloat16 storage uses one
+// float16 / bfloat16 product.
 typedef unsigned short v8u __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int SP_T = 32;       // tile edge = MFMA block
-constexpr int SP_THETA = 32;   // angles per candidate pass
 constexpr int SP_K = 16;       // samples per matrix product
+constexpr int SP_NK = 64 + SP_K;  // staging slots: one batch + one padded group
 
-__device__ __forceinline__ unsigned bf16_rne(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+__device__ __forceinline__ unsigned bf16_bits(float x) {
+  return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)x);
 }
-__device__ __forceinline__ float bf16_to_f(unsigned h) { return __uint_as_float(h << 16); }
-// hi | lo << 16, hi + lo ~ x to ~2^-17
+// hi | lo << 16 with hi + lo ~ x to ~2^-17 (round-to-nearest conversions)
 __device__ __forceinline__ unsigned bf16_split(float x) {
-  const unsigned hi = bf16_rne(x);
-  const unsigned lo = bf16_rne(x - bf16_to_f(hi));
-  return hi | (lo << 16);
+  const __bf16 h = (__bf16)x;
+  return bf16_bits(x) | (bf16_bits(x - (float)h) << 16);
 }
 __device__ __forceinline__ unsigned f16_bits(float x) {
   return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
+}
+__device__ __forceinline__ int med3i(int a, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(lo), "v"(hi));
+  return r;
 }
 
 template <int PREC>
@@ -382,14 +399,18 @@ template <int M, int PREC>
 __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
                                                float2* __restrict__ G, int slab0) {
   constexpr int W = 2 * M;
-  constexpr int NSEG = SP_THETA * SEG_SLOTS;
-  __shared__ int seg_pre[NSEG + 1];
-  __shared__ int seg_info[NSEG];
-  __shared__ int seg_mlo[NSEG];
-  __shared__ int seg_tot[SP_THETA];
-  __shared__ int st_lx[64 + SP_K], st_ly[64 + SP_K];  // local column / row of tap 0
-  __shared__ unsigned st_a[64 * W];  // y-weights (PREC 0: hi | lo << 16, else 16-bit value)
-  __shared__ uint2 st_b[64 * W];     // c * x-weights: (re, im), same encoding
+  constexpr int WS = W + 2;  // slot: zero, W taps, zero
+  // row weight: bf16 hi | lo (PREC 0) or one 16-bit value; column value:
+  // (re, im) as hi | lo words (PREC 0) or re | im << 16
+  typedef typename std::conditional<PREC == 0, unsigned, unsigned short>::type TA;
+  typedef typename std::conditional<PREC == 0, uint2, unsigned>::type TB;
+  constexpr int SA = sizeof(TA), SB = sizeof(TB);
+  __shared__ int seg_len[64];
+  __shared__ int seg_mlo[64];
+  __shared__ int seg_th[64];
+  __shared__ __align__(16) int st_l[SP_NK];  // ly * SA (low 16 bits) | lx * SB << 16
+  __shared__ TA st_a[SP_NK * WS];
+  __shared__ TB st_b[SP_NK * WS];
   const int lane = threadIdx.x;
   const int l = slab0 + blockIdx.y;
   const int ntx = p.grid / SP_T;
@@ -397,7 +418,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   const int X0 = -(p.grid >> 1) + tx * SP_T;
   const int Y0 = -(p.grid >> 1) + ty * SP_T;
   const float gcl = p.gs * (float)l;
-  const float e2b = expf(-2.f * p.beta);
+  const float e2b = __expf(-2.f * p.beta);
   const int half_m = (p.w_p >> 1) - 1;
   const int r = lane & 31;           // tile row of A / tile column of B held by this lane
   const int kq = (lane >> 5) * 8;    // first of the lane's 8 samples within a group of 16
@@ -411,142 +432,151 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
     rx[s3] = x0 < reach && x0 + (float)(SP_T + 2 * M) > -reach;
     ry[s3] = y0 < reach && y0 + (float)(SP_T + 2 * M) > -reach;
   }
+  for (int k = lane; k < SP_NK; k += 64) {
+    st_a[k * WS] = TA{};
+    st_a[k * WS + W + 1] = TA{};
+    st_b[k * WS] = TB{};
+    st_b[k * WS + W + 1] = TB{};
+  }
   v16f cre = {}, cim = {};
 
-  // candidate i of the current pass: segment search, position, value load
-  auto fetch = [&](int i, int total, SpreadCand& cd) {
-    cd.use = false;
-    cd.lx = cd.ly = 0;
-    cd.X = cd.Y = 0.f;
-    cd.c = make_float2(0.f, 0.f);
-    if (i >= total) return;
-    int lo = 0, hi = NSEG;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (seg_pre[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    const int info = seg_info[lo];
-    const int th = info & 0xFFFF;
-    const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
-    const int m = seg_mlo[lo] + (i - seg_pre[lo]);
-    sample_pos(p.ncw, gcl, p.trig[th], m, cd.X, cd.Y);
-    cd.lx = (int)floorf(cd.X) - M + 1 - sx * p.grid - X0;
-    cd.ly = (int)floorf(cd.Y) - M + 1 - sy * p.grid - Y0;
-    cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
-    if (cd.use)
-      cd.c = ld_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)), p.storage_dtype);
-  };
-
-  for (int th0 = 0; th0 < p.n_theta; th0 += SP_THETA) {
-    __syncthreads();
-    if (lane < SP_THETA) {
-      const int th = th0 + lane;
-      int q = 0, mine = 0;
-      if (th < p.n_theta) {
-        const float2 cs = p.trig[th];
-        for (int sy = -1; sy <= 1; ++sy)
-          for (int sx = -1; sx <= 1; ++sx) {
-            int mlo, mhi;
-            if (!rx[sx + 1] || !ry[sy + 1]) continue;
-            if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid - M),
-                                (float)(Y0 + sy * p.grid - M), (float)(SP_T + 2 * M),
-                                (float)(SP_T + 2 * M), half_m, mlo, mhi)) {
-              seg_info[lane * SEG_SLOTS + q] = th | ((sx + 1) << 16) | ((sy + 1) << 18);
-              seg_mlo[lane * SEG_SLOTS + q] = mlo;
-              seg_pre[lane * SEG_SLOTS + q] = mhi - mlo + 1;
-              mine += mhi - mlo + 1;
-              ++q;
+  for (int sy = -1; sy <= 1; ++sy) {
+    if (!ry[sy + 1]) continue;
+    for (int sx = -1; sx <= 1; ++sx) {
+      if (!rx[sx + 1]) continue;
+      const float bx0 = (float)(X0 + sx * p.grid - M), by0 = (float)(Y0 + sy * p.grid - M);
+      const int ox = sx * p.grid + X0, oy = sy * p.grid + Y0;  // copy origin
+      for (int th0 = 0; th0 < p.n_theta; th0 += 64) {
+        const int th = th0 + lane;
+        int mlo = 0, mhi = -1;
+        const bool found = th < p.n_theta &&
+                           tile_candidates(p.ncw, gcl, p.trig[th], bx0, by0, (float)(SP_T + 2 * M),
+                                           (float)(SP_T + 2 * M), half_m, mlo, mhi);
+        const unsigned long long fm = __ballot(found);
+        const int nseg = __popcll(fm);
+        if (nseg == 0) continue;
+        __syncthreads();
+        if (found) {
+          const int j = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+          seg_len[j] = mhi - mlo + 1;
+          seg_mlo[j] = mlo;
+          seg_th[j] = th;
+        }
+        __syncthreads();
+        // lane j holds interval j: first candidate index, first m, angle
+        const int len = lane < nseg ? seg_len[lane] : 0;
+        const int smlo = seg_mlo[lane];
+        const int sth = seg_th[lane];
+        int incl = len;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int t = __shfl_up(incl, o);
+          if (lane >= o) incl += t;
+        }
+        const int spre = incl - len;
+        const int total = __shfl(incl, 63);
+        int jcur = 0;  // interval holding candidate `base`
+        // candidate base + lane: interval, position, value
+        auto fetch = [&](int base, SpreadCand& cd) {
+          const int i = base + lane;
+          int j = jcur;
+          for (int jj = jcur + 1; jj < nseg; ++jj) {
+            const int s0 = __builtin_amdgcn_readlane(spre, jj);
+            if (s0 > base + 63) break;
+            if (s0 <= i) j = jj;
+          }
+          jcur = __builtin_amdgcn_readlane(j, 63);
+          cd.use = false;
+          cd.lx = cd.ly = 0;
+          cd.X = cd.Y = 0.f;
+          cd.c = make_float2(0.f, 0.f);
+          const int pj = __shfl(spre, j), mj = __shfl(smlo, j), tj = __shfl(sth, j);
+          if (i >= total) return;
+          const int m = mj + (i - pj);
+          sample_pos(p.ncw, gcl, p.trig[tj], m, cd.X, cd.Y);
+          cd.lx = (int)floorf(cd.X) - M + 1 - ox;
+          cd.ly = (int)floorf(cd.Y) - M + 1 - oy;
+          cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
+          if (cd.use)
+            cd.c = ld_c(D, ((size_t)l * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)), p.storage_dtype);
+        };
+        SpreadCand cur;
+        fetch(0, cur);
+        for (int base = 0; base < total; base += 64) {
+          // stage the candidates whose taps reach the tile
+          const unsigned long long mask = __ballot(cur.use);
+          const int cnt = __popcll(mask);
+          const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+          if (cur.use) {
+            float wx[W], wy[W];
+            gauss_taps<M>(cur.X - floorf(cur.X), p.beta, e2b, wx);
+            gauss_taps<M>(cur.Y - floorf(cur.Y), p.beta, e2b, wy);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+              if constexpr (PREC == 0) {
+                st_a[pos * WS + 1 + k] = bf16_split(wy[k]);
+                st_b[pos * WS + 1 + k] =
+                    make_uint2(bf16_split(cur.c.x * wx[k]), bf16_split(cur.c.y * wx[k]));
+              } else if constexpr (PREC == 1) {
+                st_a[pos * WS + 1 + k] = (unsigned short)f16_bits(wy[k]);
+                st_b[pos * WS + 1 + k] = f16_bits(cur.c.x * wx[k]) | (f16_bits(cur.c.y * wx[k]) << 16);
+              } else {
+                st_a[pos * WS + 1 + k] = (unsigned short)bf16_bits(wy[k]);
+                st_b[pos * WS + 1 + k] = bf16_bits(cur.c.x * wx[k]) | (bf16_bits(cur.c.y * wx[k]) << 16);
+              }
+            }
+            st_l[pos] = (int)(((unsigned)(cur.ly * SA) & 0xFFFFu) | ((unsigned)(cur.lx * SB) << 16));
+          }
+          // padding samples of the last group read only zeros
+          if (lane < SP_K)
+            st_l[cnt + lane] = (int)(((unsigned)(-1024 * SA) & 0xFFFFu) | ((unsigned)(-1024 * SB) << 16));
+          __syncthreads();
+          // the next batch's loads are in flight during the products below
+          fetch(base + 64, cur);
+          for (int g0 = 0; g0 < cnt; g0 += SP_K) {
+            const int4 q0 = *reinterpret_cast<const int4*>(&st_l[g0 + kq]);
+            const int4 q1 = *reinterpret_cast<const int4*>(&st_l[g0 + kq + 4]);
+            const int lk[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+            // byte offset of the lane's tap in slot g0 + kq + t, clamped onto the zeros
+            const int oa = (g0 + kq) * WS * SA, ob = (g0 + kq) * WS * SB;
+            const int ra = oa + (r + 1) * SA, rb = ob + (r + 1) * SB;
+            const int ha = oa + (W + 1) * SA, hb = ob + (W + 1) * SB;
+            const char* ca = reinterpret_cast<const char*>(st_a);
+            const char* cb = reinterpret_cast<const char*>(st_b);
+            v8u ah, al, brh, brl, bih, bil;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int ia = med3i(ra - (int)(short)(lk[t] & 0xFFFF), oa, ha);
+              const int ib = med3i(rb - (lk[t] >> 16), ob, hb);
+              const TA a = *reinterpret_cast<const TA*>(ca + ia + t * WS * SA);
+              const TB b = *reinterpret_cast<const TB*>(cb + ib + t * WS * SB);
+              if constexpr (PREC == 0) {
+                ah[t] = (unsigned short)(a & 0xFFFFu);
+                al[t] = (unsigned short)(a >> 16);
+                brh[t] = (unsigned short)(b.x & 0xFFFFu);
+                brl[t] = (unsigned short)(b.x >> 16);
+                bih[t] = (unsigned short)(b.y & 0xFFFFu);
+                bil[t] = (unsigned short)(b.y >> 16);
+              } else {
+                ah[t] = a;
+                brh[t] = (unsigned short)(b & 0xFFFFu);
+                bih[t] = (unsigned short)(b >> 16);
+              }
+            }
+            cre = mfma16<PREC>(ah, brh, cre);
+            cim = mfma16<PREC>(ah, bih, cim);
+            if constexpr (PREC == 0) {
+              cre = mfma16<PREC>(ah, brl, cre);
+              cim = mfma16<PREC>(ah, bil, cim);
+              cre = mfma16<PREC>(al, brh, cre);
+              cim = mfma16<PREC>(al, bih, cim);
             }
           }
-      }
-      for (; q < SEG_SLOTS; ++q) seg_pre[lane * SEG_SLOTS + q] = 0;
-      seg_tot[lane] = mine;
-    }
-    __syncthreads();
-    if (lane == 0) {
-      int run = 0;
-      for (int t = 0; t < SP_THETA; ++t) {
-        const int c = seg_tot[t];
-        seg_tot[t] = run;
-        run += c;
-      }
-      seg_pre[NSEG] = run;
-    }
-    __syncthreads();
-    if (lane < SP_THETA) {
-      int run = seg_tot[lane];
-      for (int q = 0; q < SEG_SLOTS; ++q) {
-        const int c = seg_pre[lane * SEG_SLOTS + q];
-        seg_pre[lane * SEG_SLOTS + q] = run;
-        run += c;
-      }
-    }
-    __syncthreads();
-    const int total = seg_pre[NSEG];
-    SpreadCand cur;
-    fetch(lane, total, cur);
-    for (int base = 0; base < total; base += 64) {
-      // stage the candidates whose taps reach the tile
-      const unsigned long long mask = __ballot(cur.use);
-      const int cnt = __popcll(mask);
-      const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-      if (cur.use) {
-        float wx[W], wy[W];
-        gauss_taps<M>(cur.X - floorf(cur.X), p.beta, e2b, wx);
-        gauss_taps<M>(cur.Y - floorf(cur.Y), p.beta, e2b, wy);
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-          if (PREC == 0) {
-            st_a[pos * W + k] = bf16_split(wy[k]);
-            st_b[pos * W + k] =
-                make_uint2(bf16_split(cur.c.x * wx[k]), bf16_split(cur.c.y * wx[k]));
-          } else if (PREC == 1) {
-            st_a[pos * W + k] = f16_bits(wy[k]);
-            st_b[pos * W + k] = make_uint2(f16_bits(cur.c.x * wx[k]), f16_bits(cur.c.y * wx[k]));
-          } else {
-            st_a[pos * W + k] = bf16_rne(wy[k]);
-            st_b[pos * W + k] = make_uint2(bf16_rne(cur.c.x * wx[k]), bf16_rne(cur.c.y * wx[k]));
-          }
-        }
-        st_lx[pos] = cur.lx;
-        st_ly[pos] = cur.ly;
-      }
-      // padding samples of the last group contribute nothing
-      if (lane < SP_K) {
-        st_lx[cnt + lane] = -(1 << 20);
-        st_ly[cnt + lane] = -(1 << 20);
-      }
-      __syncthreads();
-      // the next batch's loads are in flight during the products below
-      fetch(base + 64 + lane, total, cur);
-      for (int g0 = 0; g0 < cnt; g0 += SP_K) {
-        v8u ah, al, brh, brl, bih, bil;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int k = g0 + kq + t;
-          const int ia = r - st_ly[k];
-          const int ib = r - st_lx[k];
-          const unsigned a = (unsigned)ia < (unsigned)W ? st_a[k * W + ia] : 0u;
-          const uint2 b = (unsigned)ib < (unsigned)W ? st_b[k * W + ib] : make_uint2(0u, 0u);
-          ah[t] = (unsigned short)(a & 0xFFFFu);
-          al[t] = (unsigned short)(a >> 16);
-          brh[t] = (unsigned short)(b.x & 0xFFFFu);
-          brl[t] = (unsigned short)(b.x >> 16);
-          bih[t] = (unsigned short)(b.y & 0xFFFFu);
-          bil[t] = (unsigned short)(b.y >> 16);
-        }
-        cre = mfma16<PREC>(ah, brh, cre);
-        cim = mfma16<PREC>(ah, bih, cim);
-        if (PREC == 0) {
-          cre = mfma16<PREC>(ah, brl, cre);
-          cim = mfma16<PREC>(ah, bil, cim);
-          cre = mfma16<PREC>(al, brh, cre);
-          cim = mfma16<PREC>(al, bih, cim);
+          __syncthreads();
         }
       }
-      __syncthreads();
     }
   }
   // accumulator v of lane: tile row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
