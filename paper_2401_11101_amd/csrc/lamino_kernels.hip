@@ -27,8 +27,6 @@ constexpr int NT = 256;        // threads per block (x3 transform, interpolation
 constexpr int NTF = 512;       // threads per block of the FFT kernels
 constexpr int LDS_CPLX = 4096; // complex values per FFT block buffer (two buffers: 64 KB)
 constexpr int TILE_MAX = 64;   // gridding tile edge
-constexpr int SEG_THETA = 128; // angles per candidate pass
-constexpr int SEG_SLOTS = 9;   // periodic copies of a tile per angle
 
 // ------------------------------------------------------------ load/store
 __device__ __forceinline__ float2 ld_c(const void* p, size_t i, int dt) {
@@ -243,77 +241,6 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
 }
 
 // ================================================================ gridding
-// Candidate list shared by spreading and interpolation: for SEG_THETA
-// angles at a time, each angle contributes up to SEG_SLOTS m-intervals (one
-// per periodic copy of the tile that its sample line can reach).
-struct SegLists {
-  int pre[SEG_THETA * SEG_SLOTS + 1];
-  int info[SEG_THETA * SEG_SLOTS];  // theta | (sx+1) << 16 | (sy+1) << 18
-  int mlo[SEG_THETA * SEG_SLOTS];
-  int tot[SEG_THETA];
-};
-
-// Build the lists for angles [th0, th0 + SEG_THETA); returns the sample
-// count.  margin_lo / ext: the box [x0 + sx N_g - margin_lo, ... + ext).
-__device__ int build_segments(SegLists& S, const KParams& p, int th0, float gcl, int X0, int Y0,
-                              float margin_lo, float ext) {
-  const int tid = threadIdx.x;
-  const int half_m = (p.w_p >> 1) - 1;
-  int mine = 0;
-  if (tid < SEG_THETA) {
-    const int th = th0 + tid;
-    int q = 0;
-    if (th < p.n_theta) {
-      const float2 cs = p.trig[th];
-      for (int sy = -1; sy <= 1; ++sy)
-        for (int sx = -1; sx <= 1; ++sx) {
-          int mlo, mhi;
-          if (tile_candidates(p.ncw, gcl, cs, (float)(X0 + sx * p.grid) - margin_lo,
-                              (float)(Y0 + sy * p.grid) - margin_lo, ext, ext, half_m, mlo, mhi)) {
-            S.info[tid * SEG_SLOTS + q] = th | ((sx + 1) << 16) | ((sy + 1) << 18);
-            S.mlo[tid * SEG_SLOTS + q] = mlo;
-            S.pre[tid * SEG_SLOTS + q] = mhi - mlo + 1;  // count for now
-            mine += mhi - mlo + 1;
-            ++q;
-          }
-        }
-    }
-    for (; q < SEG_SLOTS; ++q) S.pre[tid * SEG_SLOTS + q] = 0;
-    S.tot[tid] = mine;
-  }
-  __syncthreads();
-  // inclusive scan of the per-angle totals (Hillis-Steele)
-  for (int off = 1; off < SEG_THETA; off <<= 1) {
-    int v = 0;
-    if (tid < SEG_THETA && tid >= off) v = S.tot[tid - off];
-    __syncthreads();
-    if (tid < SEG_THETA) S.tot[tid] += v;
-    __syncthreads();
-  }
-  if (tid < SEG_THETA) {
-    int run = tid ? S.tot[tid - 1] : 0;
-    for (int q = 0; q < SEG_SLOTS; ++q) {
-      const int c = S.pre[tid * SEG_SLOTS + q];
-      S.pre[tid * SEG_SLOTS + q] = run;
-      run += c;
-    }
-  }
-  if (tid == 0) S.pre[SEG_THETA * SEG_SLOTS] = S.tot[SEG_THETA - 1];
-  __syncthreads();
-  return S.pre[SEG_THETA * SEG_SLOTS];
-}
-
-// Largest s with pre[s] <= i.
-__device__ __forceinline__ int find_segment(const SegLists& S, int i) {
-  int lo = 0, hi = SEG_THETA * SEG_SLOTS;  // pre[lo] <= i < pre[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (S.pre[mid] <= i) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // Gaussian weights exp(-beta d^2) at the 2M taps d = (1 - M) - f, ..., M - f
 // by the recurrence w_{i+1} = w_i r_i, r_{i+1} = r_i exp(-2 beta).
 template <int M>
@@ -405,9 +332,6 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   typedef typename std::conditional<PREC == 0, unsigned, unsigned short>::type TA;
   typedef typename std::conditional<PREC == 0, uint2, unsigned>::type TB;
   constexpr int SA = sizeof(TA), SB = sizeof(TB);
-  __shared__ int seg_len[64];
-  __shared__ int seg_mlo[64];
-  __shared__ int seg_th[64];
   __shared__ __align__(16) int st_l[SP_NK];  // ly * SA (low 16 bits) | lx * SB << 16
   __shared__ TA st_a[SP_NK * WS];
   __shared__ TB st_b[SP_NK * WS];
@@ -455,19 +379,14 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
         const unsigned long long fm = __ballot(found);
         const int nseg = __popcll(fm);
         if (nseg == 0) continue;
-        __syncthreads();
-        if (found) {
-          const int j = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-          seg_len[j] = mhi - mlo + 1;
-          seg_mlo[j] = mlo;
-          seg_th[j] = th;
-        }
-        __syncthreads();
-        // lane j holds interval j: first candidate index, first m, angle
-        const int len = lane < nseg ? seg_len[lane] : 0;
-        const int smlo = seg_mlo[lane];
-        const int sth = seg_th[lane];
+        // compact: found lanes to 0 .. nseg-1 in lane order, the rest after;
+        // lane j then holds interval j: length, first m, angle
+        const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+        const int dst = 4 * (found ? below : nseg + lane - below);
+        const int len = __builtin_amdgcn_ds_permute(dst, found ? mhi - mlo + 1 : 0);
+        const int smlo = __builtin_amdgcn_ds_permute(dst, mlo);
+        const int sth = __builtin_amdgcn_ds_permute(dst, th);
         int incl = len;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -593,60 +512,110 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
 // Forward USFFT step (3): interpolate slab (slab0 + blockIdx.y) of the grid
 // at the samples whose wrapped base cell floor(X), floor(Y) lies in tile
 // blockIdx.x; the padded tile is staged in LDS.  Each sample has exactly
-// one owner tile, so D is written once per sample.
+// one owner tile, so D is written once per sample.  The block's four waves
+// take interleaved passes of 64 angles; a pass finds the m-interval of each
+// angle that can own samples in the tile (box widened by one cell), compacts
+// the non-empty intervals over the wave's lanes, and walks the candidates
+// 64 at a time, one per lane.
 template <int M>
 __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restrict__ G,
                                                void* __restrict__ D, int slab0, int tile) {
-  constexpr int PMAX = TILE_MAX + 2 * M - 1;
+  constexpr int W = 2 * M;
+  constexpr int PMAX = TILE_MAX + W - 1;
+  constexpr int NW = NT / 64;
   __shared__ float2 st[PMAX * PMAX];
-  __shared__ SegLists S;
-  const int P = tile + 2 * M - 1;
+  const int P = tile + W - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l = slab0 + blockIdx.y;
   const int ntx = p.grid / tile;
   const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
   const int X0 = -(p.grid >> 1) + tx * tile;
   const int Y0 = -(p.grid >> 1) + ty * tile;
   const float gcl = p.gs * (float)l;
-  const float e2b = expf(-2.f * p.beta);
+  const float e2b = __expf(-2.f * p.beta);
+  const int half_m = (p.w_p >> 1) - 1;
   const size_t gbase = (size_t)blockIdx.y * p.grid * p.grid;
   for (int e = threadIdx.x; e < P * P; e += NT) {
     const int yy = e / P, xx = e - yy * P;
     const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
     st[e] = G[gbase + (size_t)ky * p.grid + kx];
   }
-  for (int th0 = 0; th0 < p.n_theta; th0 += SEG_THETA) {
-    __syncthreads();
-    const int total = build_segments(S, p, th0, gcl, X0, Y0, 1.0f, (float)(tile + 2));
-    for (int i = threadIdx.x; i < total; i += NT) {
-      const int s = find_segment(S, i);
-      const int info = S.info[s];
-      const int th = info & 0xFFFF;
-      const int sx = ((info >> 16) & 3) - 1, sy = ((info >> 18) & 3) - 1;
-      const int m = S.mlo[s] + (i - S.pre[s]);
-      float X, Y;
-      const float2 cs = p.trig[th];
-      sample_pos(p.ncw, gcl, cs, m, X, Y);
-      const float fXf = floorf(X), fYf = floorf(Y);
-      const int bx = (int)fXf - sx * p.grid - X0;
-      const int by = (int)fYf - sy * p.grid - Y0;
-      if (bx < 0 || bx >= tile || by < 0 || by >= tile) continue;  // not this tile's sample
-      float wx[2 * M], wy[2 * M];
-      gauss_taps<M>(X - fXf, p.beta, e2b, wx);
-      gauss_taps<M>(Y - fYf, p.beta, e2b, wy);
-      float2 acc = make_float2(0.f, 0.f);
+  __syncthreads();
+  const float reach = sqrtf(0.25f * (float)p.grid * (float)p.grid + gcl * gcl) + 2.f;
+  bool rx[3], ry[3];
 #pragma unroll
-      for (int j = 0; j < 2 * M; ++j) {
-        float2 row = make_float2(0.f, 0.f);
-        const float2* src = st + (by + j) * P + bx;
+  for (int s3 = 0; s3 < 3; ++s3) {
+    const float x0 = (float)(X0 + (s3 - 1) * p.grid - 1), y0 = (float)(Y0 + (s3 - 1) * p.grid - 1);
+    rx[s3] = x0 < reach && x0 + (float)(tile + 2) > -reach;
+    ry[s3] = y0 < reach && y0 + (float)(tile + 2) > -reach;
+  }
+  for (int sy = -1; sy <= 1; ++sy) {
+    if (!ry[sy + 1]) continue;
+    for (int sx = -1; sx <= 1; ++sx) {
+      if (!rx[sx + 1]) continue;
+      const int ox = sx * p.grid + X0, oy = sy * p.grid + Y0;  // copy origin
+      for (int th0 = wave * 64; th0 < p.n_theta; th0 += NW * 64) {
+        const int th = th0 + lane;
+        int mlo = 0, mhi = -1;
+        const bool found =
+            th < p.n_theta && tile_candidates(p.ncw, gcl, p.trig[th], (float)(ox - 1), (float)(oy - 1),
+                                              (float)(tile + 2), (float)(tile + 2), half_m, mlo, mhi);
+        const unsigned long long fm = __ballot(found);
+        const int nseg = __popcll(fm);
+        if (nseg == 0) continue;
+        // compact: found lanes to 0 .. nseg-1 in lane order, the rest after
+        const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+        const int dst = 4 * (found ? below : nseg + lane - below);
+        const int len = __builtin_amdgcn_ds_permute(dst, found ? mhi - mlo + 1 : 0);
+        const int smlo = __builtin_amdgcn_ds_permute(dst, mlo);
+        const int sth = __builtin_amdgcn_ds_permute(dst, th);
+        int incl = len;
 #pragma unroll
-        for (int i2 = 0; i2 < 2 * M; ++i2) {
-          row.x = fmaf(wx[i2], src[i2].x, row.x);
-          row.y = fmaf(wx[i2], src[i2].y, row.y);
+        for (int o = 1; o < 64; o <<= 1) {
+          const int t = __shfl_up(incl, o);
+          if (lane >= o) incl += t;
         }
-        acc.x = fmaf(wy[j], row.x, acc.x);
-        acc.y = fmaf(wy[j], row.y, acc.y);
+        const int spre = incl - len;
+        const int total = __shfl(incl, 63);
+        int jcur = 0;
+        for (int base = 0; base < total; base += 64) {
+          const int i = base + lane;
+          int j = jcur;
+          for (int jj = jcur + 1; jj < nseg; ++jj) {
+            const int s0 = __builtin_amdgcn_readlane(spre, jj);
+            if (s0 > base + 63) break;
+            if (s0 <= i) j = jj;
+          }
+          jcur = __builtin_amdgcn_readlane(j, 63);
+          const int pj = __shfl(spre, j), mj = __shfl(smlo, j), tj = __shfl(sth, j);
+          if (i >= total) continue;
+          const int m = mj + (i - pj);
+          float X, Y;
+          sample_pos(p.ncw, gcl, p.trig[tj], m, X, Y);
+          const float fXf = floorf(X), fYf = floorf(Y);
+          const int bx = (int)fXf - ox;
+          const int by = (int)fYf - oy;
+          if (bx < 0 || bx >= tile || by < 0 || by >= tile) continue;  // not this tile's sample
+          float wx[W], wy[W];
+          gauss_taps<M>(X - fXf, p.beta, e2b, wx);
+          gauss_taps<M>(Y - fYf, p.beta, e2b, wy);
+          float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int jy = 0; jy < W; ++jy) {
+            float2 row = make_float2(0.f, 0.f);
+            const float2* src = st + (by + jy) * P + bx;
+#pragma unroll
+            for (int ix = 0; ix < W; ++ix) {
+              row.x = fmaf(wx[ix], src[ix].x, row.x);
+              row.y = fmaf(wx[ix], src[ix].y, row.y);
+            }
+            acc.x = fmaf(wy[jy], row.x, acc.x);
+            acc.y = fmaf(wy[jy], row.y, acc.y);
+          }
+          st_c(D, ((size_t)l * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)), acc, p.storage_dtype);
+        }
       }
-      st_c(D, ((size_t)l * p.n_theta + th) * p.w_p + (m & (p.w_p - 1)), acc, p.storage_dtype);
     }
   }
 }
