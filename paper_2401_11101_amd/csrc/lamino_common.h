@@ -73,8 +73,8 @@ LAM_HD void r4_load(const float2* a, int N, int j, float2 v[4]) {
   v[3] = a[j + 3 * q];
 }
 
-LAM_HD void r4_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
-                             bool inv, float2 v[4]) {
+// Twiddle and 4-point DFT of butterfly j in registers; outputs in v[q].
+LAM_HD void r4_compute(int j, int log2Ns, const float2* tw, int log2max, bool inv, float2 v[4]) {
   const int Ns = 1 << log2Ns;
   const int k = j & (Ns - 1);
   if (Ns > 1) {
@@ -86,11 +86,25 @@ LAM_HD void r4_compute_store(float2* a, int j, int log2Ns, const float2* tw, int
   const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
   const float2 s13 = cadd(v[1], v[3]), d13 = csub(v[1], v[3]);
   const float2 rot = inv ? mul_pi(d13) : mul_mi(d13);
-  const int o = ((j - k) << 2) + k;
-  a[o] = cadd(s02, s13);
-  a[o + Ns] = cadd(d02, rot);
-  a[o + 2 * Ns] = csub(s02, s13);
-  a[o + 3 * Ns] = csub(d02, rot);
+  v[0] = cadd(s02, s13);
+  v[1] = cadd(d02, rot);
+  v[2] = csub(s02, s13);
+  v[3] = csub(d02, rot);
+}
+
+// Output q of butterfly j goes to (j - j%Ns) R + j%Ns + q Ns.
+template <int R>
+LAM_HD void rstore(float2* a, int j, int log2Ns, const float2* v) {
+  const int Ns = 1 << log2Ns;
+  const int k = j & (Ns - 1);
+  const int o = (j - k) * R + k;
+  for (int q = 0; q < R; ++q) a[o + q * Ns] = v[q];
+}
+
+LAM_HD void r4_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[4]) {
+  r4_compute(j, log2Ns, tw, log2max, inv, v);
+  rstore<4>(a, j, log2Ns, v);
 }
 
 LAM_HD void r8_load(const float2* a, int N, int j, float2 v[8]) {
@@ -109,8 +123,7 @@ LAM_HD void dft4(float2& x0, float2& x1, float2& x2, float2& x3, bool inv) {
   x3 = csub(d02, rot);
 }
 
-LAM_HD void r8_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
-                             bool inv, float2 v[8]) {
+LAM_HD void r8_compute(int j, int log2Ns, const float2* tw, int log2max, bool inv, float2 v[8]) {
   const int Ns = 1 << log2Ns;
   const int k = j & (Ns - 1);
   if (Ns > 1) {
@@ -130,15 +143,20 @@ LAM_HD void r8_compute_store(float2* a, int j, int log2Ns, const float2* tw, int
   o2 = inv ? mul_pi(o2) : mul_mi(o2);
   o3 = inv ? make_float2(-h * (o3.x + o3.y), h * (o3.x - o3.y))
            : make_float2(h * (o3.y - o3.x), -h * (o3.x + o3.y));
-  const int o = ((j - k) << 3) + k;
-  a[o] = cadd(e0, o0);
-  a[o + Ns] = cadd(e1, o1);
-  a[o + 2 * Ns] = cadd(e2, o2);
-  a[o + 3 * Ns] = cadd(e3, o3);
-  a[o + 4 * Ns] = csub(e0, o0);
-  a[o + 5 * Ns] = csub(e1, o1);
-  a[o + 6 * Ns] = csub(e2, o2);
-  a[o + 7 * Ns] = csub(e3, o3);
+  v[0] = cadd(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[4] = csub(e0, o0);
+  v[5] = csub(e1, o1);
+  v[6] = csub(e2, o2);
+  v[7] = csub(e3, o3);
+}
+
+LAM_HD void r8_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[8]) {
+  r8_compute(j, log2Ns, tw, log2max, inv, v);
+  rstore<8>(a, j, log2Ns, v);
 }
 
 LAM_HD void r2_load(const float2* a, int N, int j, float2 v[2]) {
@@ -146,14 +164,19 @@ LAM_HD void r2_load(const float2* a, int N, int j, float2 v[2]) {
   v[1] = a[j + (N >> 1)];
 }
 
-LAM_HD void r2_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
-                             bool inv, float2 v[2]) {
+LAM_HD void r2_compute(int j, int log2Ns, const float2* tw, int log2max, bool inv, float2 v[2]) {
   const int Ns = 1 << log2Ns;
   const int k = j & (Ns - 1);
   if (Ns > 1) v[1] = cmul(v[1], twiddle(tw, k << (log2max - (log2Ns + 1)), inv));
-  const int o = ((j - k) << 1) + k;
-  a[o] = cadd(v[0], v[1]);
-  a[o + Ns] = csub(v[0], v[1]);
+  const float2 s = cadd(v[0], v[1]), d = csub(v[0], v[1]);
+  v[0] = s;
+  v[1] = d;
+}
+
+LAM_HD void r2_compute_store(float2* a, int j, int log2Ns, const float2* tw, int log2max,
+                             bool inv, float2 v[2]) {
+  r2_compute(j, log2Ns, tw, log2max, inv, v);
+  rstore<2>(a, j, log2Ns, v);
 }
 
 // ---------------------------------------------------- sample positions

@@ -25,7 +25,8 @@ namespace lam {
 
 constexpr int NT = 256;        // threads per block (x3 transform, interpolation)
 constexpr int NTF = 512;       // threads per block of the FFT kernels
-constexpr int LDS_CPLX = 4096; // complex values per FFT block buffer (two buffers: 64 KB)
+constexpr int LDS_CPLX = 4096; // complex values per FFT block (one 32 KB buffer)
+constexpr int FFT_IO = LDS_CPLX / NTF;  // loads in flight per thread when staging a block
 constexpr int TILE_MAX = 64;   // gridding tile edge
 
 // ------------------------------------------------------------ load/store
@@ -51,49 +52,71 @@ __device__ __forceinline__ void st_r(void* p, size_t i, float v, int dt) {
 }
 
 // ------------------------------------------------------------ block FFT
-// B transforms of length 2^log2N stored back to back in LDS at `a`
-// (B * N <= LDS_CPLX), with `b` as the ping-pong partner.  Returns the
-// buffer that holds the result.
-__device__ float2* block_fft(float2* a, float2* b, int log2N, int B,
-                             const float2* __restrict__ tw, int log2max, bool inv) {
+// One Stockham pass of radix R over B transforms of length N = 2^log2N in
+// place: each thread reads one butterfly's inputs, twiddles and transforms
+// them in registers, and writes the outputs after a barrier.  N / R <= NTF,
+// so a round covers NTF R / N whole transforms.
+template <int R>
+__device__ __forceinline__ void fft_pass_inplace(float2* a, int log2N, int B, int log2Ns,
+                                                 const float2* __restrict__ tw, int log2max,
+                                                 bool inv) {
+  constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int N = 1 << log2N;
-  const int np = fft_num_passes(log2N);
-  for (int p = 0; p < np; ++p) {
-    const FftPass f = fft_pass(log2N, p);
-    if (f.radix == 8) {
-      const int per = N >> 3;
-      const int total = B * per;
-      for (int t = threadIdx.x; t < total; t += NTF) {
-        const int bb = t >> (log2N - 3), j = t & (per - 1);
-        float2 v[8];
+  const int lper = log2N - LR;
+  const int per = 1 << lper;
+  const int tb = per >= NTF ? 1 : NTF >> lper;  // transforms per round
+  const int t = threadIdx.x;
+  const int j = t & (per - 1);
+  for (int b0 = 0; b0 < B; b0 += tb) {
+    const int bb = b0 + (t >> lper);
+    const bool act = t < tb * per && bb < B;
+    float2 v[R];
+    if (act) {
+      if constexpr (R == 8) {
         r8_load(a + bb * N, N, j, v);
-        r8_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
-      }
-    } else if (f.radix == 4) {
-      const int per = N >> 2;
-      const int total = B * per;
-      for (int t = threadIdx.x; t < total; t += NTF) {
-        const int bb = t >> (log2N - 2), j = t & (per - 1);
-        float2 v[4];
+        r8_compute(j, log2Ns, tw, log2max, inv, v);
+      } else if constexpr (R == 4) {
         r4_load(a + bb * N, N, j, v);
-        r4_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
-      }
-    } else {
-      const int per = N >> 1;
-      const int total = B * per;
-      for (int t = threadIdx.x; t < total; t += NTF) {
-        const int bb = t >> (log2N - 1), j = t & (per - 1);
-        float2 v[2];
+        r4_compute(j, log2Ns, tw, log2max, inv, v);
+      } else {
         r2_load(a + bb * N, N, j, v);
-        r2_compute_store(b + bb * N, j, f.log2Ns, tw, log2max, inv, v);
+        r2_compute(j, log2Ns, tw, log2max, inv, v);
       }
     }
     __syncthreads();
-    float2* t = a;
-    a = b;
-    b = t;
+    if (act) rstore<R>(a + bb * N, j, log2Ns, v);
+    __syncthreads();
   }
-  return a;
+}
+
+// B transforms of length 2^log2N stored back to back in LDS at `a`
+// (B * N <= LDS_CPLX, N <= 4096), transformed in place.
+__device__ void block_fft(float2* a, int log2N, int B, const float2* __restrict__ tw, int log2max,
+                          bool inv) {
+  const int np = fft_num_passes(log2N);
+  for (int p = 0; p < np; ++p) {
+    const FftPass f = fft_pass(log2N, p);
+    if (f.radix == 8) fft_pass_inplace<8>(a, log2N, B, f.log2Ns, tw, log2max, inv);
+    else if (f.radix == 4) fft_pass_inplace<4>(a, log2N, B, f.log2Ns, tw, log2max, inv);
+    else fft_pass_inplace<2>(a, log2N, B, f.log2Ns, tw, log2max, inv);
+  }
+}
+
+// Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places
+// it.  Each thread issues up to FFT_IO fetches before placing any of them,
+// so a block keeps many HBM requests in flight.
+template <typename T, typename Ld, typename St>
+__device__ __forceinline__ void stage_in(int total, Ld ld, St st) {
+  for (int base = 0; base < total; base += NTF * FFT_IO) {
+    T v[FFT_IO];
+#pragma unroll
+    for (int u = 0; u < FFT_IO; ++u) v[u] = ld(min(base + u * NTF + (int)threadIdx.x, total - 1));
+#pragma unroll
+    for (int u = 0; u < FFT_IO; ++u) {
+      const int e = base + u * NTF + (int)threadIdx.x;
+      if (e < total) st(e, v[u]);
+    }
+  }
 }
 
 __device__ __forceinline__ void lds_zero(float2* buf, int count) {
@@ -109,7 +132,7 @@ __device__ __forceinline__ void lds_zero(float2* buf, int count) {
 __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
                                                       int cp) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int c0 = blockIdx.x * 2 * cp;
@@ -118,15 +141,20 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   __syncthreads();
   const int wide = 2 * cp;
   float* bf = reinterpret_cast<float*>(buf);
-  for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
-    const int r = e / wide, cl = e - r * wide;
-    const int c = c0 + cl;
-    const float v = c < p.w ? ld_r(data, ((size_t)th * p.h + r) * p.w + c, p.data_dtype) : 0.f;
-    const int pos = (r - p.h / 2) & (hp - 1);
-    bf[2 * ((cl >> 1) * hp + pos) + (cl & 1)] = v;
-  }
+  const size_t row0 = (size_t)th * p.h;
+  stage_in<float>(
+      p.h * wide,
+      [&](int e) {
+        const int r = e / wide, c = c0 + e - r * wide;
+        return c < p.w ? ld_r(data, (row0 + r) * p.w + c, p.data_dtype) : 0.f;
+      },
+      [&](int e, float v) {
+        const int r = e / wide, cl = e - r * wide;
+        bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, false);
+  block_fft(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
+  const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   for (int e = threadIdx.x; e < p.n_slab * wide; e += NTF) {
     const int l = e / wide, cl = e - l * wide;
@@ -146,7 +174,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
                                                       int theta0, int rows) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
@@ -154,13 +182,16 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   lds_zero(buf, rows * wp);
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < rows * p.w; e += NTF) {
-    const int b = e / p.w, c = e - b * p.w;
-    const int l = l0 + b;
-    if (l < p.n_slab) buf[b * wp + ((c - p.w / 2) & (wp - 1))] = w1[base + (size_t)l * p.w + c];
-  }
+  const int nr = min(rows, p.n_slab - l0);
+  stage_in<float2>(
+      nr * p.w, [&](int e) { return w1[base + (size_t)l0 * p.w + e]; },
+      [&](int e, float2 v) {
+        const int b = e / p.w, c = e - b * p.w;
+        buf[b * wp + ((c - p.w / 2) & (wp - 1))] = v;
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, false);
+  block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
+  const float2* res = buf;
   for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e / wp, k = e - b * wp;
     const int l = l0 + b;
@@ -174,21 +205,25 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
 __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
                                                       float2* __restrict__ w1, int theta0,
                                                       int rows) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
   const int wp = p.w_p;
-  for (int e = threadIdx.x; e < rows * wp; e += NTF) {
-    const int b = e / wp, k = e - b * wp;
-    const int l = l0 + b;
-    float2 v = make_float2(0.f, 0.f);
-    if (l < p.n_slab && k != (wp >> 1))  // the Nyquist bin is not part of the sum
-      v = ld_c(D, ((size_t)l * p.n_theta + th) * wp + k, p.storage_dtype);
-    buf[e] = v;
-  }
+  stage_in<float2>(
+      rows * wp,
+      [&](int e) {
+        const int b = e >> p.log2_wp, k = e & (wp - 1);
+        const int l = l0 + b;
+        float2 v = make_float2(0.f, 0.f);
+        if (l < p.n_slab && k != (wp >> 1))  // the Nyquist bin is not part of the sum
+          v = ld_c(D, ((size_t)l * p.n_theta + th) * wp + k, p.storage_dtype);
+        return v;
+      },
+      [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_wp, rows, p.tw, p.log2_twmax, true);
+  block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
+  const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   for (int e = threadIdx.x; e < rows * p.w; e += NTF) {
     const int b = e / p.w, c = e - b * p.w;
@@ -205,7 +240,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
 __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ data, int theta0,
                                                       int cp, float scale) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int c0 = blockIdx.x * 2 * cp;
@@ -213,21 +248,29 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   lds_zero(buf, cp * hp);
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
-  for (int e = threadIdx.x; e < p.n_slab * cp; e += NTF) {
-    const int l = e / cp, pp = e - l * cp;
-    const int ca = c0 + 2 * pp, cb = ca + 1;
-    const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
-    const float2 xb = cb < p.w ? w1[base + (size_t)l * p.w + cb] : make_float2(0.f, 0.f);
-    float2* z = buf + pp * hp;
-    if (l == 0) {
-      z[0] = make_float2(xa.x, xb.x);
-    } else {
-      z[l] = make_float2(xa.x - xb.y, xa.y + xb.x);
-      z[hp - l] = make_float2(xa.x + xb.y, xb.x - xa.y);
-    }
-  }
+  stage_in<float4>(
+      p.n_slab * cp,
+      [&](int e) {
+        const int l = e / cp, pp = e - l * cp;
+        const int ca = c0 + 2 * pp, cb = ca + 1;
+        const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
+        const float2 xb = cb < p.w ? w1[base + (size_t)l * p.w + cb] : make_float2(0.f, 0.f);
+        return make_float4(xa.x, xa.y, xb.x, xb.y);
+      },
+      [&](int e, float4 x) {
+        const int l = e / cp, pp = e - l * cp;
+        float2* z = buf + pp * hp;
+        // x = (Re X_a, Im X_a, Re X_b, Im X_b)
+        if (l == 0) {
+          z[0] = make_float2(x.x, x.z);
+        } else {
+          z[l] = make_float2(x.x - x.w, x.y + x.z);
+          z[hp - l] = make_float2(x.x + x.w, x.z - x.y);
+        }
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_hp, cp, p.tw, p.log2_twmax, true);
+  block_fft(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
+  const float2* res = buf;
   const int wide = 2 * cp;
   const float* bf = reinterpret_cast<const float*>(res);
   for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
@@ -628,16 +671,16 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
 // the row then hold x1 = ix - n/2.
 __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
                                                       int rows) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
-  for (int e = threadIdx.x; e < rows * N; e += NTF) {
-    const int b = e / N;
-    buf[e] = (r0 + b < N) ? g[(size_t)(r0 + b) * N + (e - b * N)] : make_float2(0.f, 0.f);
-  }
+  stage_in<float2>(
+      min(rows, N - r0) * N, [&](int e) { return g[(size_t)r0 * N + e]; },
+      [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, true);
+  block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
+  const float2* res = buf;
   for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
     const int b = e / p.n, ix = e - b * p.n;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
@@ -646,16 +689,23 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
 
 __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
                                                       void* __restrict__ g, int slab0, int cols) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float2* gg = G + (size_t)blockIdx.y * N * N;
-  for (int e = threadIdx.x; e < cols * N; e += NTF) {
-    const int k2 = e / cols, c = e - k2 * cols;
-    buf[c * N + k2] = (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
-  }
+  stage_in<float2>(
+      cols * N,
+      [&](int e) {
+        const int k2 = e / cols, c = e - k2 * cols;
+        return (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int k2 = e / cols, c = e - k2 * cols;
+        buf[c * N + k2] = v;
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, true);
+  block_fft(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
+  const float2* res = buf;
   const int l = slab0 + blockIdx.y;
   for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
     const int y = e / cols, c = e - y * cols;
@@ -668,21 +718,27 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
 
 __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const int l = slab0 + blockIdx.y;
   lds_zero(buf, cols * N);
   __syncthreads();
-  for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
-    const int y = e / cols, c = e - y * cols;
-    const int ix = ix0 + c;
-    if (ix >= p.n) continue;
-    const float2 v = ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype);
-    buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
-  }
+  stage_in<float2>(
+      cols * p.n,
+      [&](int e) {
+        const int y = e / cols, ix = ix0 + e - y * cols;
+        return ix < p.n ? ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype)
+                        : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int y = e / cols, c = e - y * cols;
+        const int ix = ix0 + c;
+        if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, cols, p.tw, p.log2_twmax, false);
+  block_fft(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
+  const float2* res = buf;
   float2* gg = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < cols * N; e += NTF) {
     const int k2 = e / cols, c = e - k2 * cols;
@@ -692,18 +748,25 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
 
 __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
                                                       int rows) {
-  __shared__ float2 buf[2 * LDS_CPLX];
+  __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
   lds_zero(buf, rows * N);
   __syncthreads();
-  for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
-    const int b = e / p.n, ix = e - b * p.n;
-    if (r0 + b < N) buf[b * N + ((ix - p.n / 2) & (N - 1))] = g[(size_t)(r0 + b) * N + ix];
-  }
+  stage_in<float2>(
+      min(rows, N - r0) * p.n,
+      [&](int e) {
+        const int b = e / p.n, ix = e - b * p.n;
+        return g[(size_t)(r0 + b) * N + ix];
+      },
+      [&](int e, float2 v) {
+        const int b = e / p.n, ix = e - b * p.n;
+        buf[b * N + ((ix - p.n / 2) & (N - 1))] = v;
+      });
   __syncthreads();
-  const float2* res = block_fft(buf, buf + LDS_CPLX, p.log2_grid, rows, p.tw, p.log2_twmax, false);
+  block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
+  const float2* res = buf;
   for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e / N;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + (e - b * N)] = res[e];
