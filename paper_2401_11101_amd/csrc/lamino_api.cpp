@@ -70,6 +70,33 @@ void layout_work(lamino_plan_s* p) {
   p->work_bytes = off;
 }
 
+int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Round-to-nearest-even bfloat16 / float16 bits of x.
+unsigned short to_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+float from_bf16(unsigned short h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+// x ~ hi + lo with hi, lo 16-bit floats (bfloat16, or float16 if f16)
+void split16(double x, bool f16, unsigned short& hi, unsigned short& lo) {
+  if (f16) {
+    const _Float16 h = (_Float16)x;
+    const _Float16 l = (_Float16)(x - (double)h);
+    std::memcpy(&hi, &h, 2);
+    std::memcpy(&lo, &l, 2);
+  } else {
+    hi = to_bf16((float)x);
+    lo = to_bf16((float)(x - (double)from_bf16(hi)));
+  }
+}
+
 void build_tables(lamino_plan_s* p) {
   const double phi = p->tilt;
   const double cphi = std::cos(phi);
@@ -85,8 +112,12 @@ void build_tables(lamino_plan_s* p) {
   p->off_filt_fbp = take((size_t)p->w_p * 4);
   p->off_filt_adj = take((size_t)p->w_p * 4);
   p->off_deapod = take((size_t)p->n * 4);
-  p->off_e_adj = take((size_t)p->nz * p->n_slab * 8);
-  p->off_e_fwd = take((size_t)p->n_slab * p->nz * 8);
+  p->x3a_rows = round_up(p->nz, 32);
+  p->x3a_k = round_up(2 * p->n_slab, 16);
+  p->x3f_rows = round_up(2 * p->n_slab, 32);
+  p->x3f_k = round_up(p->nz, 16);
+  p->off_x3a = take((size_t)2 * p->x3a_rows * p->x3a_k * 2);
+  p->off_x3f = take((size_t)2 * p->x3f_rows * p->x3f_k * 2);
   p->off_tw = take((size_t)twmax * 8);
   p->table_bytes = off;
   p->host_tables.assign(off, 0);
@@ -117,18 +148,30 @@ void build_tables(lamino_plan_s* p) {
     deap[i] = (float)(std::sqrt(p->beta / M_PI) *
                       std::exp(M_PI * M_PI * x * x / (p->beta * (double)p->grid * p->grid)));
   }
-  // x3 phases: xi3 = l cos(phi) / h_p (eq:uneqspace)
-  float* ea = reinterpret_cast<float*>(base + p->off_e_adj);
-  float* ef = reinterpret_cast<float*>(base + p->off_e_fwd);
+  // x3 phases: xi3 = l cos(phi) / h_p (eq:uneqspace), as hi + lo pairs of
+  // 16-bit values for the matrix-core x3 transforms.  Fragment-major layout:
+  // entry (row, k) sits at ((k / 16 * rows + row) * 2 + k % 16 / 8) * 8 + k % 8,
+  // so the 8-value operand of every lane of a 32-row tile is one contiguous run.
+  unsigned short* xa = reinterpret_cast<unsigned short*>(base + p->off_x3a);
+  unsigned short* xf = reinterpret_cast<unsigned short*>(base + p->off_x3f);
+  const size_t pa = (size_t)p->x3a_rows * p->x3a_k, pf = (size_t)p->x3f_rows * p->x3f_k;
+  auto frag = [](size_t rows, size_t row, size_t k) {
+    return ((k / 16 * rows + row) * 2 + (k % 16) / 8) * 8 + k % 8;
+  };
+  const bool f16a = p->opts.storage_dtype == LAMINO_F16;
   for (int z = 0; z < p->nz; ++z) {
     const double x3 = z - p->nz / 2;
     for (int l = 0; l < p->n_slab; ++l) {
       const double a = 2.0 * M_PI * x3 * l * cphi / p->h_p;
       const double wl = l == 0 ? 1.0 : 2.0;
-      ea[2 * ((size_t)z * p->n_slab + l)] = (float)(wl * std::cos(a));
-      ea[2 * ((size_t)z * p->n_slab + l) + 1] = (float)(wl * std::sin(a));
-      ef[2 * ((size_t)l * p->nz + z)] = (float)std::cos(a);
-      ef[2 * ((size_t)l * p->nz + z) + 1] = (float)(-std::sin(a));
+      const double va[2] = {wl * std::cos(a), -wl * std::sin(a)};
+      const double vf[2] = {std::cos(a), -std::sin(a)};
+      for (int c = 0; c < 2; ++c) {
+        const size_t ia = frag(p->x3a_rows, z, 2 * l + c);
+        split16(va[c], f16a, xa[ia], xa[pa + ia]);
+        const size_t jf = frag(p->x3f_rows, 2 * l + c, z);
+        split16(vf[c], false, xf[jf], xf[pf + jf]);
+      }
     }
   }
   float* tw = reinterpret_cast<float*>(base + p->off_tw);
@@ -171,8 +214,12 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.trig = reinterpret_cast<const float2*>(t + p->off_trig);
   k.filt = reinterpret_cast<const float*>(t + (fbp_filter ? p->off_filt_fbp : p->off_filt_adj));
   k.deapod = reinterpret_cast<const float*>(t + p->off_deapod);
-  k.e_adj = reinterpret_cast<const float2*>(t + p->off_e_adj);
-  k.e_fwd = reinterpret_cast<const float2*>(t + p->off_e_fwd);
+  k.x3a = reinterpret_cast<const unsigned short*>(t + p->off_x3a);
+  k.x3f = reinterpret_cast<const unsigned short*>(t + p->off_x3f);
+  k.x3a_rows = p->x3a_rows;
+  k.x3a_k = p->x3a_k;
+  k.x3f_rows = p->x3f_rows;
+  k.x3f_k = p->x3f_k;
   k.tw = reinterpret_cast<const float2*>(t + p->off_tw);
   return k;
 }

@@ -23,8 +23,14 @@ struct KParams {
   const float2* trig;     // [n_theta] (cos, sin)
   const float* filt;      // [w_p] transfer function incl. 1/(h_p w_p)
   const float* deapod;    // [n] psi correction per axis
-  const float2* e_adj;    // [nz][n_slab] w_l exp(+2 pi i x3 l cos(phi)/h_p)
-  const float2* e_fwd;    // [n_slab][nz] exp(-2 pi i x3 l cos(phi)/h_p)
+  // x3 transform operands (matrix-core layout, 16-bit hi and lo planes):
+  //   adj: A[z][2l + c] = w_l (cos a, -sin a)[c], a = 2 pi x3 l cos(phi) / h_p,
+  //        rows padded to x3a_rows, K = x3a_k; bf16 (f16 for float16 storage)
+  //   fwd: A[2l + c][z] = (cos a, -sin a)[c], rows x3f_rows, K = x3f_k; bf16
+  //   fragment-major: (row, k) at ((k / 16 * rows + row) * 2 + k % 16 / 8) * 8 + k % 8
+  const unsigned short* x3a;  // [2][x3a_rows][x3a_k]
+  const unsigned short* x3f;  // [2][x3f_rows][x3f_k]
+  int x3a_rows, x3a_k, x3f_rows, x3f_k;
   const float2* tw;       // [2^log2_twmax] exp(-2 pi i t / 2^log2_twmax)
 };
 
@@ -41,7 +47,8 @@ struct lamino_plan_s {
   double beta;
   int z_chunk, slab_chunk, theta_chunk;
   // table layout (bytes)
-  size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_e_adj, off_e_fwd, off_tw;
+  size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_x3a, off_x3f, off_tw;
+  int x3a_rows, x3a_k, x3f_rows, x3f_k;
   size_t table_bytes;
   int log2_twmax;
   // workspace layout (bytes)

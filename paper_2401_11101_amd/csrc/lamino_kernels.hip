@@ -774,118 +774,146 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
 }
 
 // ============================================================ x3 transform
-// vol[z][col] = sum_l Re(e_adj[z][l] g[l][col]), z in [z0, z0 + nzc).
-// Block: 64 z x 64 columns, thread 4 x 4 outputs, l in chunks of 16.
-constexpr int XT = 64, XK = 16;
+// Both directions are real matrix products on the matrix cores, with the
+// phase tables split on the host into 16-bit hi + lo parts:
+//   adj: vol[z][col] = sum_k A[z][k] B[k][col], k = 2l + c,
+//        B[2l][col] = Re g[l][col], B[2l + 1][col] = Im g[l][col];
+//   fwd: G[2l + c][col] = sum_z A[2l + c][z] f[z][col] gives Re / Im ghat.
+// A wave computes X3_ZT row tiles of 32 x 32 (v_mfma_f32_32x32x16) that
+// share one column tile, so each B fragment is loaded and split once; four
+// waves per block along the rows.  Lane l holds A[l % 32][8 (l / 32) + t],
+// B[8 (l / 32) + t][l % 32] and C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
+// Float32 operands are split into bf16 hi + lo (three products); float16 /
+// bfloat16 slab data are exact in their own format (two products).
+constexpr int X3_WAVES = 4;
+constexpr int X3_ZT = 2;
+constexpr int X3_ROWS = 32 * X3_ZT * X3_WAVES;  // rows per block
 
-__global__ __launch_bounds__(NT) void k_x3_adj(KParams p, const void* __restrict__ g,
-                                               float* __restrict__ vol, int z0, int nzc) {
-  __shared__ float2 Es[XT][XK + 1];
-  __shared__ float2 Gs[XK][XT];
-  const int ncol = p.n * p.n;
-  const int col0 = blockIdx.x * XT;
-  const int zb = blockIdx.y * XT;
-  const int tc = threadIdx.x & 15, tz = threadIdx.x >> 4;
-  float acc[4][4];
+__device__ __forceinline__ void split8(const float x[8], v8u& hi, v8u& lo) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
-  for (int l0 = 0; l0 < p.n_slab; l0 += XK) {
-    for (int e = threadIdx.x; e < XT * XK; e += NT) {
-      const int zz = e / XK, ll = e - zz * XK;
-      const int z = z0 + zb + zz, l = l0 + ll;
-      Es[zz][ll] = (zb + zz < nzc && l < p.n_slab) ? p.e_adj[(size_t)z * p.n_slab + l]
-                                                    : make_float2(0.f, 0.f);
-    }
-    for (int e = threadIdx.x; e < XT * XK; e += NT) {
-      const int ll = e / XT, cc = e - ll * XT;
-      const int l = l0 + ll, col = col0 + cc;
-      Gs[ll][cc] = (l < p.n_slab && col < ncol) ? ld_c(g, (size_t)l * ncol + col, p.storage_dtype)
-                                                 : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int ll = 0; ll < XK; ++ll) {
-      float2 ev[4], gv[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) ev[a] = Es[tz * 4 + a][ll];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) gv[b] = Gs[ll][tc + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = fmaf(ev[a].x, gv[b].x, fmaf(-ev[a].y, gv[b].y, acc[a][b]));
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int zz = zb + tz * 4 + a;
-    if (zz >= nzc) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int col = col0 + tc + 16 * b;
-      if (col < ncol) vol[(size_t)(z0 + zz) * ncol + col] = acc[a][b];
-    }
+  for (int t = 0; t < 8; ++t) {
+    const unsigned s2 = bf16_split(x[t]);
+    hi[t] = (unsigned short)(s2 & 0xFFFFu);
+    lo[t] = (unsigned short)(s2 >> 16);
   }
 }
 
-// ghat[l][col] = sum_z e_fwd[l][z] f[z][col]; block 64 l x 64 columns.
-__global__ __launch_bounds__(NT) void k_x3_fwd(KParams p, const float* __restrict__ f,
-                                               void* __restrict__ g) {
-  __shared__ float2 Es[XT][XK + 1];
-  __shared__ float Fs[XK][XT];
+// A fragment of tile row `row` (clamped into the table) at K-step s
+__device__ __forceinline__ void load_afrag(const unsigned short* tab, int rows, int K, int row,
+                                           int h, int s, v8u& hi, v8u& lo) {
+  const size_t o = (((size_t)s * rows + row) * 2 + h) * 8;
+  hi = *reinterpret_cast<const v8u*>(tab + o);
+  lo = *reinterpret_cast<const v8u*>(tab + (size_t)rows * K + o);
+}
+
+// vol[z0 + z][col] for z in [0, nzc)
+template <int PREC>
+__global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void* __restrict__ g,
+                                                          float* __restrict__ vol, int z0,
+                                                          int nzc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
   const int ncol = p.n * p.n;
-  const int col0 = blockIdx.x * XT;
-  const int lb = blockIdx.y * XT;
-  const int tc = threadIdx.x & 15, tl = threadIdx.x >> 4;
-  float2 acc[4][4];
+  const int col = blockIdx.x * 32 + r;
+  const int zt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;
+  if (zt >= nzc) return;
+  const int K = p.x3a_k;
+  int arow[X3_ZT];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int i = 0; i < X3_ZT; ++i) arow[i] = min(z0 + zt + 32 * i + r, p.x3a_rows - 1);
+  const bool cok = col < ncol;
+  const size_t cidx = cok ? col : 0;
+  v16f acc[X3_ZT] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int l0 = (k0 >> 1) + 4 * h;  // this lane's slabs l0 .. l0 + 3
+    v8u bh, bl;
+    if constexpr (PREC == 0) {
+      float x[8];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-  for (int z0 = 0; z0 < p.nz; z0 += XK) {
-    for (int e = threadIdx.x; e < XT * XK; e += NT) {
-      const int ll = e / XK, zz = e - ll * XK;
-      const int l = lb + ll, z = z0 + zz;
-      Es[ll][zz] = (l < p.n_slab && z < p.nz) ? p.e_fwd[(size_t)l * p.nz + z] : make_float2(0.f, 0.f);
+      for (int q = 0; q < 4; ++q) {
+        const int l = l0 + q;
+        float2 v = make_float2(0.f, 0.f);
+        if (cok && l < p.n_slab) v = reinterpret_cast<const float2*>(g)[(size_t)l * ncol + cidx];
+        x[2 * q] = v.x;
+        x[2 * q + 1] = v.y;
+      }
+      split8(x, bh, bl);
+    } else {
+      // 16-bit complex pairs (re | im << 16) are the operand's pairs of k
+      uint4 u;
+      unsigned* uu = reinterpret_cast<unsigned*>(&u);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int l = l0 + q;
+        uu[q] = (cok && l < p.n_slab) ? reinterpret_cast<const unsigned*>(g)[(size_t)l * ncol + cidx]
+                                      : 0u;
+      }
+      bh = __builtin_bit_cast(v8u, u);
     }
-    for (int e = threadIdx.x; e < XT * XK; e += NT) {
-      const int zz = e / XT, cc = e - zz * XT;
-      const int z = z0 + zz, col = col0 + cc;
-      Fs[zz][cc] = (z < p.nz && col < ncol) ? f[(size_t)z * ncol + col] : 0.f;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int zz = 0; zz < XK; ++zz) {
-      float2 ev[4];
-      float fv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) ev[a] = Es[tl * 4 + a][zz];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) fv[b] = Fs[zz][tc + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x = fmaf(ev[a].x, fv[b], acc[a][b].x);
-          acc[a][b].y = fmaf(ev[a].y, fv[b], acc[a][b].y);
-        }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int l = lb + tl * 4 + a;
-    if (l >= p.n_slab) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int col = col0 + tc + 16 * b;
-      if (col < ncol) st_c(g, (size_t)l * ncol + col, acc[a][b], p.storage_dtype);
+    for (int i = 0; i < X3_ZT; ++i) {
+      v8u ah, al;
+      load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, k0 >> 4, ah, al);
+      acc[i] = mfma16<PREC>(ah, bh, acc[i]);
+      acc[i] = mfma16<PREC>(al, bh, acc[i]);
+      if constexpr (PREC == 0) acc[i] = mfma16<0>(ah, bl, acc[i]);
     }
   }
+  if (!cok) return;
+#pragma unroll
+  for (int i = 0; i < X3_ZT; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (z < nzc) vol[(size_t)(z0 + z) * ncol + col] = acc[i][v];
+    }
+}
+
+// ghat[l][col] = sum_z exp(-2 pi i x3 l cos(phi) / h_p) f[z][col]
+__global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float* __restrict__ f,
+                                                          void* __restrict__ g) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int ncol = p.n * p.n;
+  const int col = blockIdx.x * 32 + r;
+  const int mt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;  // rows 2l + c
+  if (mt >= 2 * p.n_slab) return;
+  const int K = p.x3f_k;
+  int arow[X3_ZT];
+#pragma unroll
+  for (int i = 0; i < X3_ZT; ++i) arow[i] = min(mt + 32 * i + r, p.x3f_rows - 1);
+  const bool cok = col < ncol;
+  const size_t cidx = cok ? col : 0;
+  v16f acc[X3_ZT] = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    float x[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int z = k0 + 8 * h + t;
+      x[t] = (cok && z < p.nz) ? f[(size_t)z * ncol + cidx] : 0.f;
+    }
+    v8u bh, bl;
+    split8(x, bh, bl);
+#pragma unroll
+    for (int i = 0; i < X3_ZT; ++i) {
+      v8u ah, al;
+      load_afrag(p.x3f, p.x3f_rows, K, arow[i], h, k0 >> 4, ah, al);
+      acc[i] = mfma16<0>(ah, bh, acc[i]);
+      acc[i] = mfma16<0>(ah, bl, acc[i]);
+      acc[i] = mfma16<0>(al, bh, acc[i]);
+    }
+  }
+  if (!cok) return;
+  // rows 2l (re) and 2l + 1 (im) sit in accumulators v and v + 1 (v % 4 = 0, 2)
+#pragma unroll
+  for (int i = 0; i < X3_ZT; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) {
+      const int m = mt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int l = m >> 1;
+      if (l < p.n_slab)
+        st_c(g, (size_t)l * ncol + col, make_float2(acc[i][v], acc[i][v + 1]), p.storage_dtype);
+    }
 }
 
 // ================================================================ drivers
@@ -976,8 +1004,13 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   for (int z0 = 0; z0 < p->nz; z0 += p->z_chunk) {
     const int nzc = std::min(p->z_chunk, p->nz - z0);
     StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
-    hipLaunchKernelGGL(k_x3_adj, dim3(cdiv(ncol, XT), cdiv(nzc, XT)), dim3(NT), 0, s, kp,
-                       (const void*)g, d_vol, z0, nzc);
+    const dim3 grid(cdiv(ncol, 32), cdiv(nzc, X3_ROWS));
+    if (kp.storage_dtype == LAMINO_F32)
+      hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
+    else if (kp.storage_dtype == LAMINO_F16)
+      hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
+    else
+      hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
   }
   return hipGetLastError();
 }
@@ -991,8 +1024,8 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   const int ncol = p->n * p->n;
   {
     StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
-    hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, XT), cdiv(p->n_slab, XT)), dim3(NT), 0, s, kp,
-                       d_vol, g);
+    hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, 32), cdiv(2 * p->n_slab, X3_ROWS)),
+                       dim3(64 * X3_WAVES), 0, s, kp, d_vol, g);
   }
   const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
   const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
