@@ -91,6 +91,31 @@ def algorithmic_work(info, storage_bytes, data_bytes):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fbp_256cube_400proj_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11101_amd", "csrc", f)
+                  for f in ("lamino_kernels.hip", "lamino_common.h")]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the kernel sources changed after the counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"<!-- traffic kernel=(.+?) bytes=(\d+) source=([0-9a-f]+) -->", text)
+    if not m or m.group(1) != kernel:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return int(m.group(2)) if h.hexdigest()[:16] == m.group(3) else None
+
+
 def roofline(stages, work, steps):
     """Dominant stage against its peak: algorithmic work per launch (work per
     FBP / launches per FBP) over the mean launch duration from the events."""
@@ -102,9 +127,11 @@ def roofline(stages, work, steps):
     if name == "gridding":
         # matrix-core gridding: algorithmic taps as float32 vector work
         achieved = w["flops"] / per_fbp / (per_launch_ms * 1e-3) / 1e12
-        return {"kernel": "k_spread (gridding)", "bound": "alu", "achieved": round(achieved, 3),
+        return {"kernel": "k_spread<5, 0> (gridding)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic("k_spread<5, 0>"),
+                "algorithmic_bytes": w["bytes"]}
     achieved = w["bytes"] / per_fbp / (per_launch_ms * 1e-3) / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}

@@ -74,8 +74,13 @@ typedef struct {
 /* Options; zero-initialise and then call lamino_opts_default. */
 typedef struct {
   int data_dtype;     /* lamino_dtype of d                                    */
-  int storage_dtype;  /* lamino_dtype of the stored spectra and slab planes;
-                         arithmetic is always float32                         */
+  int storage_dtype;  /* lamino_dtype of the stored spectra and slab planes.
+                         Accumulation is float32 throughout.  Gridding and
+                         the x3 transform multiply on the matrix cores: with
+                         float32 storage each operand is split into bfloat16
+                         hi + lo parts (three products, ~2^-17 relative
+                         error); float16 / bfloat16 storage multiplies the
+                         stored values directly                               */
   int filter;         /* lamino_filter used by lamino_fbp                      */
   double pad_u, pad_v;/* detector padding factors (>= 1), default 2           */
   int kernel_m;       /* Gaussian half-width M in grid cells (2..8); 0 picks
