@@ -1,8 +1,11 @@
 """GPU parity: the HIP operators against the CPU oracle, through the C ABI."""
+import functools
+
 import numpy as np
 import pytest
 import torch
 
+import synth
 from helpers import TOL_F32, TOL_LOWP, dev, ellipsoid_data, rel, to_dev, to_np
 from oracle import filters, nudft
 from oracle.geometry import Geometry, freqs
@@ -152,3 +155,47 @@ def test_c2_full_size_sampled_columns():
     e = rel(vol[:, ys, xs], ref)
     print(f"c2 sampled columns rel-L2 {e:.2e}")
     assert e < TOL_F32
+
+
+@functools.lru_cache(maxsize=1)
+def _quarter_c3():
+    # the large-chunk geometry at 1/4 scale: detector 256 wide x 128 rows,
+    # 375 projections, tilt 20 deg, volume 128 x 256 x 256, ellipsoids with
+    # log-normal speckle 0.1, data stored as float16
+    nz, n, nt, h, w = 128, 256, 375, 128, 256
+    phi = np.deg2rad(20)
+    ells = synth.random_ellipsoids(20, nz, n, seed=0)
+    d = synth.project_ellipsoids(ells, nt, h, w, phi, device=dev(), dtype=torch.float64)
+    d = synth.apply_speckle(d, 0.1, seed=1)
+    d16 = d.cpu().numpy().astype(np.float16)
+    return Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=phi), d16
+
+
+def test_c3_quarter_scale_fp16_sampled_columns():
+    g, d16 = _quarter_c3()
+    plan = Plan(g.nz, g.n, g.n_theta, g.h, g.w, g.phi, data_dtype="f16", storage_dtype="f16",
+                z_chunk=16)
+    vol = to_np(plan.fbp(torch.from_numpy(d16).to(dev())))
+    G = nudft.filter_spectra(nudft.data_spectra_fft(d16.astype(np.float64), g), g,
+                             filters.SHEPP_LOGAN)
+    ys = np.array([0, 61, 128, 190, 255])
+    xs = np.array([5, 128, 97, 250, 255])
+    ref = nudft.backproject_columns(G, g, ys, xs)
+    e = rel(vol[:, ys, xs], ref)
+    print(f"quarter-scale large-chunk geometry, fp16: sampled columns rel-L2 {e:.2e}")
+    assert e < TOL_LOWP
+
+
+def test_c3_quarter_scale_chunked_equals_unchunked():
+    g, d16 = _quarter_c3()
+    D = torch.from_numpy(d16).to(dev())
+    whole = Plan(g.nz, g.n, g.n_theta, g.h, g.w, g.phi, data_dtype="f16", storage_dtype="f16")
+    parts = Plan(g.nz, g.n, g.n_theta, g.h, g.w, g.phi, data_dtype="f16", storage_dtype="f16",
+                 z_chunk=16, slab_chunk=24, theta_chunk=50)
+    a, b = to_np(whole.fbp(D)), to_np(parts.fbp(D))
+    print(f"chunked vs whole: rel-L2 {rel(b, a):.2e}")
+    assert rel(b, a) < 1e-6
+    f = np.random.default_rng(3).standard_normal((g.nz, g.n, g.n)).astype(np.float32)
+    F = torch.from_numpy(f).to(dev())
+    a, b = to_np(whole.fwd(F)), to_np(parts.fwd(F))
+    assert rel(b, a) < 1e-6
