@@ -232,6 +232,35 @@ LAM_HD bool tile_candidates(float ncw, float gcl, float2 cs, float x0, float y0,
   return mlo <= mhi;
 }
 
+// Tile order for the gridding launches: rank 0 .. ntx^2 - 1 -> tile (tx, ty)
+// in square rings around the grid centre, innermost first.  Samples are
+// densest near the centre (polar sampling), so the longest-running tiles
+// start first.  ntx is 1 or even.
+LAM_HD void ring_tile(int rank, int ntx, int& tx, int& ty) {
+  if (ntx == 1) {
+    tx = ty = 0;
+    return;
+  }
+  int k = 0;  // ring k holds ranks (2k)^2 .. (2k + 2)^2 - 1
+  while ((2 * k + 2) * (2 * k + 2) <= rank) ++k;
+  const int q = rank - 4 * k * k;
+  const int s = 2 * k + 2;  // side of the ring
+  const int lo = ntx / 2 - 1 - k, hi = ntx / 2 + k;
+  if (q < s) {
+    tx = lo + q;
+    ty = lo;
+  } else if (q < 2 * s - 1) {
+    tx = hi;
+    ty = lo + 1 + (q - s);
+  } else if (q < 3 * s - 2) {
+    tx = hi - 1 - (q - (2 * s - 1));
+    ty = hi;
+  } else {
+    tx = lo;
+    ty = hi - 1 - (q - (3 * s - 2));
+  }
+}
+
 // Wrap an integer grid coordinate to [-N/2, N/2) (N a power of two).
 LAM_HD int wrap_centred(int k, int N) { return ((k + (N >> 1)) & (N - 1)) - (N >> 1); }
 

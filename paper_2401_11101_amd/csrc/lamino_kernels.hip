@@ -303,7 +303,10 @@ __device__ __forceinline__ void gauss_taps(float f, float beta, float e2b, float
 //     G_tile += wy_s (c_s wx_s)^T,
 // wy_s / wx_s the sample's Gaussian weights on the tile rows / columns (zero
 // outside its 2M taps), so a batch of K samples is one 32 x 32 x K matrix
-// product with the tile held in MFMA accumulators.  One wave per tile.
+// product with the tile held in MFMA accumulators.  One wave per tile; the
+// launch grid is (slab, tile rank) with slabs varying fastest and tiles in
+// centre-out rings, so the densest tiles of every slab start first and the
+// sparse outer tiles fill the tail.
 //
 // Candidates: for each periodic copy of the tile that the slab's samples can
 // reach and each pass of 64 angles, lane j finds the m-interval of angle j
@@ -328,7 +331,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int SP_T = 32;       // tile edge = MFMA block
 constexpr int SP_K = 16;       // samples per matrix product
-constexpr int SP_NK = 64 + SP_K;  // staging slots: one batch + one padded group
+constexpr int SP_NK = 64;        // staging slots: one batch of candidates
 
 __device__ __forceinline__ unsigned bf16_bits(float x) {
   return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)x);
@@ -376,12 +379,13 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   typedef typename std::conditional<PREC == 0, uint2, unsigned>::type TB;
   constexpr int SA = sizeof(TA), SB = sizeof(TB);
   __shared__ __align__(16) int st_l[SP_NK];  // ly * SA (low 16 bits) | lx * SB << 16
-  __shared__ TA st_a[SP_NK * WS];
-  __shared__ TB st_b[SP_NK * WS];
+  __shared__ TA st_a[64 * WS];
+  __shared__ TB st_b[64 * WS];
   const int lane = threadIdx.x;
-  const int l = slab0 + blockIdx.y;
+  const int l = slab0 + blockIdx.x;  // slabs vary fastest, dense central tiles first
   const int ntx = p.grid / SP_T;
-  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  int tx, ty;
+  ring_tile(blockIdx.y, ntx, tx, ty);
   const int X0 = -(p.grid >> 1) + tx * SP_T;
   const int Y0 = -(p.grid >> 1) + ty * SP_T;
   const float gcl = p.gs * (float)l;
@@ -399,7 +403,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
     rx[s3] = x0 < reach && x0 + (float)(SP_T + 2 * M) > -reach;
     ry[s3] = y0 < reach && y0 + (float)(SP_T + 2 * M) > -reach;
   }
-  for (int k = lane; k < SP_NK; k += 64) {
+  for (int k = lane; k < 64; k += 64) {
     st_a[k * WS] = TA{};
     st_a[k * WS + W + 1] = TA{};
     st_b[k * WS] = TB{};
@@ -430,6 +434,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
         const int len = __builtin_amdgcn_ds_permute(dst, found ? mhi - mlo + 1 : 0);
         const int smlo = __builtin_amdgcn_ds_permute(dst, mlo);
         const int sth = __builtin_amdgcn_ds_permute(dst, th);
+        const float2 cst = p.trig[min(sth, p.n_theta - 1)];  // interval's angle
         int incl = len;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -454,9 +459,10 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
           cd.X = cd.Y = 0.f;
           cd.c = make_float2(0.f, 0.f);
           const int pj = __shfl(spre, j), mj = __shfl(smlo, j), tj = __shfl(sth, j);
+          const float2 cs = make_float2(__shfl(cst.x, j), __shfl(cst.y, j));
           if (i >= total) return;
           const int m = mj + (i - pj);
-          sample_pos(p.ncw, gcl, p.trig[tj], m, cd.X, cd.Y);
+          sample_pos(p.ncw, gcl, cs, m, cd.X, cd.Y);
           cd.lx = (int)floorf(cd.X) - M + 1 - ox;
           cd.ly = (int)floorf(cd.Y) - M + 1 - oy;
           cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
             st_l[pos] = (int)(((unsigned)(cur.ly * SA) & 0xFFFFu) | ((unsigned)(cur.lx * SB) << 16));
           }
           // padding samples of the last group read only zeros
-          if (lane < SP_K)
+          if (lane < SP_K && cnt + lane < 64)
             st_l[cnt + lane] = (int)(((unsigned)(-1024 * SA) & 0xFFFFu) | ((unsigned)(-1024 * SB) << 16));
           __syncthreads();
           // the next batch's loads are in flight during the products below
@@ -542,7 +548,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
     }
   }
   // accumulator v of lane: tile row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
-  float2* g = G + (size_t)blockIdx.y * p.grid * p.grid;
+  float2* g = G + (size_t)blockIdx.x * p.grid * p.grid;
   const int kx = (X0 + r) & (p.grid - 1);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -552,9 +558,9 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   }
 }
 
-// Forward USFFT step (3): interpolate slab (slab0 + blockIdx.y) of the grid
+// Forward USFFT step (3): interpolate slab (slab0 + blockIdx.x) of the grid
 // at the samples whose wrapped base cell floor(X), floor(Y) lies in tile
-// blockIdx.x; the padded tile is staged in LDS.  Each sample has exactly
+// ring_tile(blockIdx.y); the padded tile is staged in LDS.  Each sample has exactly
 // one owner tile, so D is written once per sample.  The block's four waves
 // take interleaved passes of 64 angles; a pass finds the m-interval of each
 // angle that can own samples in the tile (box widened by one cell), compacts
@@ -569,15 +575,16 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
   __shared__ float2 st[PMAX * PMAX];
   const int P = tile + W - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l = slab0 + blockIdx.y;
+  const int l = slab0 + blockIdx.x;  // slabs vary fastest, dense central tiles first
   const int ntx = p.grid / tile;
-  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  int tx, ty;
+  ring_tile(blockIdx.y, ntx, tx, ty);
   const int X0 = -(p.grid >> 1) + tx * tile;
   const int Y0 = -(p.grid >> 1) + ty * tile;
   const float gcl = p.gs * (float)l;
   const float e2b = __expf(-2.f * p.beta);
   const int half_m = (p.w_p >> 1) - 1;
-  const size_t gbase = (size_t)blockIdx.y * p.grid * p.grid;
+  const size_t gbase = (size_t)blockIdx.x * p.grid * p.grid;
   for (int e = threadIdx.x; e < P * P; e += NT) {
     const int yy = e / P, xx = e - yy * P;
     const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
@@ -926,17 +933,17 @@ static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, i
                           hipStream_t s) {
   const int tiles = (kp.grid / SP_T) * (kp.grid / SP_T);
   if (kp.storage_dtype == LAMINO_F32)
-    hipLaunchKernelGGL((k_spread<M, 0>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 0>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
   else if (kp.storage_dtype == LAMINO_F16)
-    hipLaunchKernelGGL((k_spread<M, 1>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 1>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
   else
-    hipLaunchKernelGGL((k_spread<M, 2>), dim3(tiles, ns), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 2>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
 }
 template <int M>
 static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, int ns, int tile,
                           hipStream_t s) {
   const int tiles = (kp.grid / tile) * (kp.grid / tile);
-  hipLaunchKernelGGL(k_interp<M>, dim3(tiles, ns), dim3(NT), 0, s, kp, G, D, s0, tile);
+  hipLaunchKernelGGL(k_interp<M>, dim3(ns, tiles), dim3(NT), 0, s, kp, G, D, s0, tile);
 }
 
 static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns,

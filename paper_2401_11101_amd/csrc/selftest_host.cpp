@@ -8,7 +8,9 @@
 //          (gridding), and every sample is owned by exactly one tile through
 //          its wrapped base cell, inside that tile's candidate interval
 //          (interpolation).
+//  ring    the centre-out tile order is a bijection onto the ntx x ntx tiles.
 // Prints one line per check and exits non-zero on the first failure.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -144,8 +146,33 @@ static int check_candidates() {
   return 0;
 }
 
+static int check_ring_order() {
+  for (int ntx = 1; ntx <= 128; ntx = ntx == 1 ? 2 : 2 * ntx) {
+    std::vector<int> seen(ntx * ntx, 0);
+    int prev = -1;
+    for (int r = 0; r < ntx * ntx; ++r) {
+      int tx, ty;
+      ring_tile(r, ntx, tx, ty);
+      if (tx < 0 || tx >= ntx || ty < 0 || ty >= ntx || seen[ty * ntx + tx]++) {
+        std::printf("ring ntx=%d rank=%d -> (%d, %d) FAIL\n", ntx, r, tx, ty);
+        return 1;
+      }
+      // Chebyshev distance from the centre never decreases along the order
+      const int d = std::max(std::max(tx - ntx / 2, ntx / 2 - 1 - tx), std::max(ty - ntx / 2, ntx / 2 - 1 - ty));
+      if (ntx > 1 && d < prev) {
+        std::printf("ring ntx=%d rank=%d not centre-out FAIL\n", ntx, r);
+        return 1;
+      }
+      prev = d;
+    }
+  }
+  std::printf("ring ok\n");
+  return 0;
+}
+
 int main() {
   if (check_fft()) return 1;
   if (check_candidates()) return 1;
+  if (check_ring_order()) return 1;
   return 0;
 }
