@@ -102,6 +102,11 @@ typedef struct {
   size_t table_bytes, work_bytes;
   size_t off_spectra, bytes_spectra; /* D[l][theta][k] in the workspace       */
   size_t off_slabs, bytes_slabs;     /* g[l][y][x] in the workspace           */
+  double spectra_scale; /* power of two by which the stored D and g of the
+                           adjoint / FBP direction exceed their definition:
+                           h_p w_p / 64 for F16 storage (keeps typical values
+                           out of the float16 subnormal range), else 1; the
+                           x3 transform removes it from the output            */
 } lamino_info;
 
 /* Fill *opts with defaults (F32 data and storage, Shepp-Logan, pad 2). */

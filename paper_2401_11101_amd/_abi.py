@@ -80,6 +80,7 @@ class lamino_info(ctypes.Structure):
         ("bytes_spectra", ctypes.c_size_t),
         ("off_slabs", ctypes.c_size_t),
         ("bytes_slabs", ctypes.c_size_t),
+        ("spectra_scale", ctypes.c_double),
     ]
 
 

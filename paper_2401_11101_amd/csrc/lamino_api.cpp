@@ -132,7 +132,11 @@ void build_tables(lamino_plan_s* p) {
   // the Nyquist bin k = w_p / 2 is not part of the sums.
   float* ffbp = reinterpret_cast<float*>(base + p->off_filt_fbp);
   float* fadj = reinterpret_cast<float*>(base + p->off_filt_adj);
-  const double norm = 1.0 / ((double)p->h_p * p->w_p);
+  // Float16 storage: the filtered spectra carry an extra power-of-two factor
+  // s = h_p w_p / 64 (exact), which keeps their typical magnitudes away from
+  // the float16 subnormal range; the x3 transform multiplies its output by 1/s.
+  p->spectra_scale = p->opts.storage_dtype == LAMINO_F16 ? (double)p->h_p * p->w_p / 64.0 : 1.0;
+  const double norm = p->spectra_scale / ((double)p->h_p * p->w_p);
   for (int k = 0; k < p->w_p; ++k) {
     const int m = k < p->w_p / 2 ? k : k - p->w_p;
     const double km = (double)m / p->w_p;
@@ -216,6 +220,7 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.deapod = reinterpret_cast<const float*>(t + p->off_deapod);
   k.x3a = reinterpret_cast<const unsigned short*>(t + p->off_x3a);
   k.x3f = reinterpret_cast<const unsigned short*>(t + p->off_x3f);
+  k.x3_out_scale = (float)(1.0 / p->spectra_scale);
   k.x3a_rows = p->x3a_rows;
   k.x3a_k = p->x3a_k;
   k.x3f_rows = p->x3f_rows;
@@ -418,6 +423,7 @@ int lamino_plan_info(const lamino_plan_t* p, lamino_info* info) {
   info->off_spectra = p->off_D;
   info->bytes_spectra = p->bytes_D;
   info->off_slabs = p->off_g;
+  info->spectra_scale = p->spectra_scale;
   info->bytes_slabs = p->bytes_g;
   return LAMINO_OK;
 }

@@ -31,6 +31,7 @@ struct KParams {
   const unsigned short* x3a;  // [2][x3a_rows][x3a_k]
   const unsigned short* x3f;  // [2][x3f_rows][x3f_k]
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
+  float x3_out_scale;     // 1 / (power-of-two factor carried by the stored spectra)
   const float2* tw;       // [2^log2_twmax] exp(-2 pi i t / 2^log2_twmax)
 };
 
@@ -48,6 +49,7 @@ struct lamino_plan_s {
   int z_chunk, slab_chunk, theta_chunk;
   // table layout (bytes)
   size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_x3a, off_x3f, off_tw;
+  double spectra_scale;  // power of two folded into the filter tables
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
   size_t table_bytes;
   int log2_twmax;

@@ -872,7 +872,7 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-      if (z < nzc) vol[(size_t)(z0 + z) * ncol + col] = acc[i][v];
+      if (z < nzc) vol[(size_t)(z0 + z) * ncol + col] = acc[i][v] * p.x3_out_scale;
     }
 }
 

@@ -119,7 +119,8 @@ class Plan:
         return _abi.lamino_plan_stage_times(self._h, reset)
 
     def spectra(self):
-        """View of the stored spectra D[l][theta][k] of the last call (complex)."""
+        """Stored spectra D[l][theta][k] after an adjoint or FBP call (complex),
+        with the storage scale (info.spectra_scale) divided out."""
         i = self.info
         raw = self.work[i.off_spectra:i.off_spectra + i.bytes_spectra]
         n_theta, h, w = self.shape_data
@@ -127,4 +128,4 @@ class Plan:
             v = raw.view(torch.float32).view(i.n_slab, n_theta, i.w_p, 2)
         else:
             v = raw.view(_DTYPES[self.storage_dtype][1]).view(i.n_slab, n_theta, i.w_p, 2).float()
-        return torch.view_as_complex(v.contiguous())
+        return torch.view_as_complex(v.contiguous()) / i.spectra_scale

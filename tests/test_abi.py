@@ -63,6 +63,19 @@ def test_plan_sizes_match_conventions(lib):
         assert info.beta == pytest.approx(math.pi * (R - 0.5) / (R * info.kernel_m))
         t, wb = _abi.lamino_plan_sizes(plan)
         assert t == info.table_bytes and wb == info.work_bytes and t % 256 == 0
+        assert info.spectra_scale == 1.0
+        _abi.lamino_plan_destroy(plan)
+
+
+def test_float16_spectra_carry_a_power_of_two_scale(lib):
+    for dt, want in [(_abi.LAMINO_F16, lambda hp, wp: hp * wp / 64), (_abi.LAMINO_BF16, lambda hp, wp: 1.0)]:
+        o = _abi.lamino_opts_default()
+        o.storage_dtype = dt
+        plan = _abi.lamino_plan(_geom(32, 32, 20, 24, 40), o)
+        info = _abi.lamino_plan_info(plan)
+        s = info.spectra_scale
+        assert s == want(info.h_p, info.w_p)
+        assert math.frexp(s)[0] == 0.5  # an exact power of two
         _abi.lamino_plan_destroy(plan)
 
 
