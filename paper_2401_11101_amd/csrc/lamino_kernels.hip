@@ -813,7 +813,36 @@ __device__ __forceinline__ void load_afrag(const unsigned short* tab, int rows, 
   lo = *reinterpret_cast<const v8u*>(tab + (size_t)rows * K + o);
 }
 
-// vol[z0 + z][col] for z in [0, nzc)
+// Raw B operand of K-step k0 for the adjoint: this lane's slabs
+// (k0 / 2 + 4 h .. + 3) of column `cidx`, float2 (PREC 0) or 16-bit pairs.
+template <int PREC>
+struct X3AdjB {
+  typedef typename std::conditional<PREC == 0, float2, unsigned>::type T;
+  T v[4];
+};
+template <int PREC>
+__device__ __forceinline__ void x3_adj_loadb(const KParams& p, const void* g, int ncol, bool cok,
+                                             size_t cidx, int k0, int h, X3AdjB<PREC>& b) {
+  const int l0 = (k0 >> 1) + 4 * h;
+  // loads from clamped indices are unconditional (no branches around them);
+  // out-of-range values are replaced afterwards
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int l = l0 + q;
+    const bool ok = cok && l < p.n_slab;
+    const size_t i = (size_t)min(l, p.n_slab - 1) * ncol + cidx;
+    if constexpr (PREC == 0) {
+      const float2 v = reinterpret_cast<const float2*>(g)[i];
+      b.v[q] = ok ? v : make_float2(0.f, 0.f);
+    } else {
+      const unsigned v = reinterpret_cast<const unsigned*>(g)[i];
+      b.v[q] = ok ? v : 0u;
+    }
+  }
+}
+
+// vol[z0 + z][col] for z in [0, nzc).  The operands of K-step k0 + 16 are
+// loaded while the products of step k0 run.
 template <int PREC>
 __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void* __restrict__ g,
                                                           float* __restrict__ vol, int z0,
@@ -831,39 +860,40 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
   const bool cok = col < ncol;
   const size_t cidx = cok ? col : 0;
   v16f acc[X3_ZT] = {};
+  X3AdjB<PREC> bc, bn;
+  v8u ahc[X3_ZT], alc[X3_ZT], ahn[X3_ZT], aln[X3_ZT];
+  x3_adj_loadb<PREC>(p, g, ncol, cok, cidx, 0, h, bc);
+#pragma unroll
+  for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, 0, ahc[i], alc[i]);
   for (int k0 = 0; k0 < K; k0 += 16) {
-    const int l0 = (k0 >> 1) + 4 * h;  // this lane's slabs l0 .. l0 + 3
+    const int kn = min(k0 + 16, K - 16);  // the last step reloads itself
+    x3_adj_loadb<PREC>(p, g, ncol, cok, cidx, kn, h, bn);
+#pragma unroll
+    for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, kn >> 4, ahn[i], aln[i]);
     v8u bh, bl;
     if constexpr (PREC == 0) {
       float x[8];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int l = l0 + q;
-        float2 v = make_float2(0.f, 0.f);
-        if (cok && l < p.n_slab) v = reinterpret_cast<const float2*>(g)[(size_t)l * ncol + cidx];
-        x[2 * q] = v.x;
-        x[2 * q + 1] = v.y;
+        x[2 * q] = bc.v[q].x;
+        x[2 * q + 1] = bc.v[q].y;
       }
       split8(x, bh, bl);
     } else {
       // 16-bit complex pairs (re | im << 16) are the operand's pairs of k
-      uint4 u;
-      unsigned* uu = reinterpret_cast<unsigned*>(&u);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int l = l0 + q;
-        uu[q] = (cok && l < p.n_slab) ? reinterpret_cast<const unsigned*>(g)[(size_t)l * ncol + cidx]
-                                      : 0u;
-      }
-      bh = __builtin_bit_cast(v8u, u);
+      bh = __builtin_bit_cast(v8u, make_uint4(bc.v[0], bc.v[1], bc.v[2], bc.v[3]));
     }
 #pragma unroll
     for (int i = 0; i < X3_ZT; ++i) {
-      v8u ah, al;
-      load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, k0 >> 4, ah, al);
-      acc[i] = mfma16<PREC>(ah, bh, acc[i]);
-      acc[i] = mfma16<PREC>(al, bh, acc[i]);
-      if constexpr (PREC == 0) acc[i] = mfma16<0>(ah, bl, acc[i]);
+      acc[i] = mfma16<PREC>(ahc[i], bh, acc[i]);
+      acc[i] = mfma16<PREC>(alc[i], bh, acc[i]);
+      if constexpr (PREC == 0) acc[i] = mfma16<0>(ahc[i], bl, acc[i]);
+    }
+    bc = bn;
+#pragma unroll
+    for (int i = 0; i < X3_ZT; ++i) {
+      ahc[i] = ahn[i];
+      alc[i] = aln[i];
     }
   }
   if (!cok) return;
