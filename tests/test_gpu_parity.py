@@ -155,6 +155,14 @@ def test_c2_full_size_sampled_columns():
     e = rel(vol[:, ys, xs], ref)
     print(f"c2 sampled columns rel-L2 {e:.2e}")
     assert e < TOL_F32
+    # the fp16-storage path on the same data (its default half-width M = 3)
+    p16 = Plan(nz, n, nt, h, w, g.phi, data_dtype="f16", storage_dtype="f16")
+    v16 = to_np(p16.fbp(torch.from_numpy(d.astype(np.float16)).to(dev())))
+    G16 = nudft.filter_spectra(nudft.data_spectra_fft(d.astype(np.float16).astype(np.float64), g), g,
+                               filters.SHEPP_LOGAN)
+    e16 = rel(v16[:, ys, xs], nudft.backproject_columns(G16, g, ys, xs))
+    print(f"c2 sampled columns, fp16 storage: rel-L2 {e16:.2e}")
+    assert e16 < TOL_LOWP
 
 
 @functools.lru_cache(maxsize=1)
