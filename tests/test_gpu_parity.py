@@ -207,3 +207,26 @@ def test_c3_quarter_scale_chunked_equals_unchunked():
     F = torch.from_numpy(f).to(dev())
     a, b = to_np(whole.fwd(F)), to_np(parts.fwd(F))
     assert rel(b, a) < 1e-6
+
+
+def test_stage_profiling_counts_launches_and_time():
+    g, plan, f, d = _pair(16, 24, 20, 16, 24, 30)
+    D = to_dev(d)
+    plan.fbp(D)
+    torch.cuda.synchronize()
+    assert all(ms == 0.0 and n == 0 for ms, n in plan.stage_times(reset=True).values())
+    plan.profile(True)
+    for _ in range(3):
+        plan.fbp(D)
+    plan.fwd(to_dev(f))
+    torch.cuda.synchronize()
+    st = plan.stage_times(reset=True)
+    plan.profile(False)
+    # per FBP: detector 2 launches, gridding 1 per slab chunk, slab 2 per chunk, x3 1 per z chunk
+    chunks = -(-plan.info.n_slab // plan.info.slab_chunk)
+    assert st["detector"][1] == 4 * 2
+    assert st["gridding"][1] == 4 * chunks
+    assert st["slab"][1] == 4 * 2 * chunks
+    assert st["x3"][1] == 4
+    assert all(ms > 0 for ms, _ in st.values())
+    assert all(n == 0 for _, n in plan.stage_times().values())
