@@ -4,18 +4,21 @@
 //   proj_cols_fwd  per projection: real column pairs -> h_p-point FFT along v
 //   proj_rows_fwd  per (projection, l): w_p-point FFT along u, filter,
 //                  store the spectrum slab-major D[l][theta][k]
-//   spread         per (slab, tile): Gaussian gridding of the slab's samples
-//                  into an LDS tile, no global atomics
+//   spread         per (slab, 32 x 32 tile): Gaussian gridding of the slab's
+//                  samples as rank-16 updates on the matrix cores, no atomics
 //   grid_rows_inv  per slab row: inverse N_g-point FFT along x1, crop
 //   grid_cols_adj  per slab column block: inverse FFT along x2, crop, psi
 //                  correction, store g[l][y][x]
 //   x3_adj         vol[z][col] = Re sum_l w_l exp(2 pi i x3 l cos(phi)/h_p) g[l][col]
+//                  as a real matrix product on the matrix cores
 // Forward projection (eq:fftfwd) runs the transposes in reverse order:
 //   x3_fwd, grid_cols_fwd, grid_rows_fwd, interp, proj_rows_inv, proj_cols_inv.
 //
-// FFTs are Stockham radix-8/4/2 passes over LDS with twiddles from a table
-// computed in double precision on the host.  All arithmetic is float32;
-// stored spectra and slab planes may be float16 / bfloat16.
+// FFTs are in-place Stockham radix-8/4/2 passes over LDS with twiddles from
+// a table computed in double precision on the host.  Accumulation is
+// float32 throughout; the matrix-core products take 16-bit operands (bf16
+// hi + lo splits for float32 data); stored spectra and slab planes may be
+// float16 / bfloat16.
 #include <type_traits>
 
 #include "lamino_common.h"
@@ -27,7 +30,7 @@ constexpr int NT = 256;        // threads per block (x3 transform, interpolation
 constexpr int NTF = 512;       // threads per block of the FFT kernels
 constexpr int LDS_CPLX = 4096; // complex values per FFT block (one 32 KB buffer)
 constexpr int FFT_IO = LDS_CPLX / NTF;  // loads in flight per thread when staging a block
-constexpr int TILE_MAX = 64;   // gridding tile edge
+constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 
 // ------------------------------------------------------------ load/store
 __device__ __forceinline__ float2 ld_c(const void* p, size_t i, int dt) {
