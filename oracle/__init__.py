@@ -18,4 +18,7 @@ direct    O1: the direct line-integral discretisation with linear
           interpolation (a C/OpenMP library, `direct.c`)
 cg        O4: conjugate gradients for the least-squares problem
           (Dai-Yuan direction + exact line search, and textbook CGLS)
+tv        O5: total-variation regularised reconstruction by ADMM
+          (forward-difference gradient, divergence, isotropic soft
+          threshold, dual update, CG on the tomography sub-problem)
 """
