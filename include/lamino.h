@@ -171,6 +171,74 @@ int lamino_plan_profile(lamino_plan_t* plan, int enable);
  * E_INVALID, E_HIP. */
 int lamino_plan_stage_times(lamino_plan_t* plan, double* ms, int* launches, int reset);
 
+/* ---------------------------------------------------------------------
+ * Total-variation regularised reconstruction (Appendix A).
+ *
+ * The problem is min 1/2 ||L mu - d||^2 + alpha sum_v |grad mu (v)|
+ * (eq:mainregproblem, isotropic TV).  Discrete operators on a float32
+ * volume vol[nz][ny][nx] (x fastest):
+ *   grad: forward differences, g[c][z][y][x] with c = 0 (x), 1 (y), 2 (z);
+ *         the last difference along each axis is 0;
+ *   div:  -grad^T (the paper defines div as the adjoint of -grad).
+ * Gradient fields are component-major float32 arrays [3][nz][ny][nx].
+ * Input and output buffers of one call must not overlap unless stated.
+ * These calls need no plan; sizes must be positive (E_INVALID) and the
+ * volume at most 2^30 tiles of 64 x 4 x 16 voxels (E_UNSUPPORTED). */
+
+/* d_grad = grad d_vol. */
+int lamino_tv_grad(const float* d_vol, float* d_grad, int nz, int ny, int nx, void* stream);
+
+/* d_out = div d_p = -grad^T d_p. */
+int lamino_tv_div(const float* d_p, float* d_out, int nz, int ny, int nx, void* stream);
+
+/* d_out = d_base - rho div(grad d_vol - d_shift): the gradient of
+ * rho/2 ||grad vol - shift||^2 added to base, i.e. the regularisation part
+ * of the sub-problem gradient Eq:gradtomo with shift = psi - lambda / rho.
+ * d_shift and d_base may be NULL (zero).  d_out may equal d_base. */
+int lamino_tv_term(const float* d_vol, const float* d_shift, const float* d_base, double rho,
+                   float* d_out, int nz, int ny, int nx, void* stream);
+
+/* The psi-step and dual update of the ADMM (Eq:reg, Eq:lamd), per voxel on
+ * the 3-vectors g = grad vol (v):
+ *   psi = shrink(g + lambda / rho, alpha / rho),
+ *         shrink(q, t) = q max(0, 1 - t / |q|)   (the minimiser of the
+ *         augmented Lagrangian eq:alagr as written: thresholds lambda/rho
+ *         and alpha/rho),
+ *   lambda <- lambda + rho (g - psi)              (d_lambda updated in place),
+ *   d_shift = psi - lambda / rho (new lambda)     (what the next sub-problem
+ *                                                  needs),
+ *   d_psi = psi if d_psi != NULL.
+ * Needs rho > 0, alpha >= 0 (E_INVALID). */
+int lamino_tv_shrink(const float* d_vol, float* d_lambda, float* d_shift, float* d_psi,
+                     double alpha, double rho, int nz, int ny, int nx, void* stream);
+
+/* Bytes of the device state buffer lamino_admm_tv needs for this plan's
+ * volume and detector (about 10 volumes plus one data array).  Host-only. */
+int lamino_admm_tv_state_bytes(const lamino_plan_t* plan, size_t* bytes);
+
+/* ADMM for eq:mainregproblem with this plan's L and L* (Appendix A).
+ * outer iterations, each:
+ *   mu <- `inner` conjugate-gradient steps on Eq:tomo from the current mu
+ *         (gradient Eq:gradtomo, Dai-Yuan direction Eq:DaiYuan2, exact line
+ *         search gamma = -<g, eta> / (||L eta||^2 + rho ||grad eta||^2),
+ *         restarted from the steepest-descent direction each iteration);
+ *   psi, lambda <- lamino_tv_shrink.
+ * A zero line-search or Dai-Yuan denominator ends that inner solve early.
+ * d_data: float32 d[n_theta][h][w] (the plan's data dtype must be F32,
+ * E_INVALID otherwise; the storage dtype may be narrower).  d_vol: the
+ * initial guess on entry, the result on exit.  d_state: caller-owned
+ * device buffer of lamino_admm_tv_state_bytes bytes, 256-byte aligned,
+ * laid out as lambda [3][nz][n][n] float32 at offset 0, then (at the next
+ * 256-byte boundary) shift = psi - lambda / rho [3][nz][n][n] float32,
+ * then work arrays.  resume == 0 starts from psi = lambda = 0 and forms
+ * L*(L mu - d) from d_vol (one L and one L*); resume != 0 continues from a
+ * previous call's state with the same plan, data, volume buffer and rho.
+ * Cost per outer iteration: `inner` (L + L*) plus bandwidth-bound volume
+ * kernels; every scalar stays on the device (no host synchronisation).
+ * Errors: E_INVALID, E_UNBOUND, E_UNSUPPORTED, E_HIP. */
+int lamino_admm_tv(const lamino_plan_t* plan, const float* d_data, float* d_vol, double alpha,
+                   double rho, int outer, int inner, int resume, void* d_state, void* stream);
+
 /* Free the host plan (device buffers stay with the caller). NULL is ok. */
 int lamino_plan_destroy(lamino_plan_t* plan);
 

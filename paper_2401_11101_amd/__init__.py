@@ -16,6 +16,10 @@ def __getattr__(name):
         from . import autograd
 
         return getattr(autograd, name)
+    if name in ("admm_tv", "AdmmTV"):
+        from . import tv
+
+        return getattr(tv, name)
     if name == "Server":
         from .serve import Server
 

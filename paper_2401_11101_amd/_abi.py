@@ -33,6 +33,12 @@ EXPORTED = (
     "lamino_plan_destroy",
     "lamino_strerror",
     "lamino_last_error",
+    "lamino_tv_grad",
+    "lamino_tv_div",
+    "lamino_tv_term",
+    "lamino_tv_shrink",
+    "lamino_admm_tv_state_bytes",
+    "lamino_admm_tv",
 )
 
 
@@ -122,9 +128,18 @@ def load_library(path=LIB_PATH):
     lib.lamino_strerror.restype = ctypes.c_char_p
     lib.lamino_last_error.argtypes = []
     lib.lamino_last_error.restype = ctypes.c_char_p
+    I, D = ctypes.c_int, ctypes.c_double
+    lib.lamino_tv_grad.argtypes = [P, P, I, I, I, P]
+    lib.lamino_tv_div.argtypes = [P, P, I, I, I, P]
+    lib.lamino_tv_term.argtypes = [P, P, P, D, P, I, I, I, P]
+    lib.lamino_tv_shrink.argtypes = [P, P, P, P, D, D, I, I, I, P]
+    lib.lamino_admm_tv_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lamino_admm_tv.argtypes = [P, P, P, D, D, I, I, I, P, P]
     for name in ("lamino_plan", "lamino_plan_sizes", "lamino_plan_info", "lamino_plan_bind",
                  "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
-                 "lamino_plan_profile", "lamino_plan_stage_times"):
+                 "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
+                 "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink",
+                 "lamino_admm_tv_state_bytes", "lamino_admm_tv"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -174,6 +189,37 @@ def lamino_fwd(plan, d_vol, d_data, stream):
 
 def lamino_adj(plan, d_data, d_vol, stream):
     _check(load_library().lamino_adj(plan, d_data, d_vol, stream), "lamino_adj")
+
+
+def lamino_tv_grad(d_vol, d_grad, nz, ny, nx, stream):
+    _check(load_library().lamino_tv_grad(d_vol, d_grad, nz, ny, nx, stream), "lamino_tv_grad")
+
+
+def lamino_tv_div(d_p, d_out, nz, ny, nx, stream):
+    _check(load_library().lamino_tv_div(d_p, d_out, nz, ny, nx, stream), "lamino_tv_div")
+
+
+def lamino_tv_term(d_vol, d_shift, d_base, rho, d_out, nz, ny, nx, stream):
+    _check(load_library().lamino_tv_term(d_vol, d_shift, d_base, float(rho), d_out, nz, ny, nx,
+                                         stream), "lamino_tv_term")
+
+
+def lamino_tv_shrink(d_vol, d_lambda, d_shift, d_psi, alpha, rho, nz, ny, nx, stream):
+    _check(load_library().lamino_tv_shrink(d_vol, d_lambda, d_shift, d_psi, float(alpha),
+                                           float(rho), nz, ny, nx, stream), "lamino_tv_shrink")
+
+
+def lamino_admm_tv_state_bytes(plan):
+    b = ctypes.c_size_t()
+    _check(load_library().lamino_admm_tv_state_bytes(plan, ctypes.byref(b)),
+           "lamino_admm_tv_state_bytes")
+    return b.value
+
+
+def lamino_admm_tv(plan, d_data, d_vol, alpha, rho, outer, inner, resume, d_state, stream):
+    _check(load_library().lamino_admm_tv(plan, d_data, d_vol, float(alpha), float(rho), int(outer),
+                                         int(inner), int(bool(resume)), d_state, stream),
+           "lamino_admm_tv")
 
 
 NSTAGE = 4

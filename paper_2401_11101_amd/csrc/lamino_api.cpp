@@ -474,6 +474,81 @@ int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* s
   return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fwd");
 }
 
+static int check_tv(const void* a, const void* b, int nz, int ny, int nx, const char* who) {
+  if (!a || !b) return fail(LAMINO_E_INVALID, "%s: NULL pointer", who);
+  if (nz <= 0 || ny <= 0 || nx <= 0)
+    return fail(LAMINO_E_INVALID, "%s: sizes must be positive (%d, %d, %d)", who, nz, ny, nx);
+  if (!lam::tv_dims_ok(nz, ny, nx))
+    return fail(LAMINO_E_UNSUPPORTED, "%s: volume %d x %d x %d too large", who, nz, ny, nx);
+  return LAMINO_OK;
+}
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int lamino_tv_grad(const float* d_vol, float* d_grad, int nz, int ny, int nx, void* stream) {
+  const int c = check_tv(d_vol, d_grad, nz, ny, nx, "lamino_tv_grad");
+  if (c) return c;
+  hipError_t e = lam::tv_grad(d_vol, d_grad, nz, ny, nx, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_tv_grad");
+}
+
+int lamino_tv_div(const float* d_p, float* d_out, int nz, int ny, int nx, void* stream) {
+  const int c = check_tv(d_p, d_out, nz, ny, nx, "lamino_tv_div");
+  if (c) return c;
+  hipError_t e = lam::tv_div(d_p, d_out, nz, ny, nx, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_tv_div");
+}
+
+int lamino_tv_term(const float* d_vol, const float* d_shift, const float* d_base, double rho,
+                   float* d_out, int nz, int ny, int nx, void* stream) {
+  const int c = check_tv(d_vol, d_out, nz, ny, nx, "lamino_tv_term");
+  if (c) return c;
+  if (!std::isfinite(rho)) return fail(LAMINO_E_INVALID, "lamino_tv_term: rho must be finite");
+  hipError_t e = lam::tv_term(d_vol, d_shift, d_base, (float)rho, d_out, nz, ny, nx,
+                              static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_tv_term");
+}
+
+int lamino_tv_shrink(const float* d_vol, float* d_lambda, float* d_shift, float* d_psi,
+                     double alpha, double rho, int nz, int ny, int nx, void* stream) {
+  int c = check_tv(d_vol, d_lambda, nz, ny, nx, "lamino_tv_shrink");
+  if (c) return c;
+  if (!d_shift) return fail(LAMINO_E_INVALID, "lamino_tv_shrink: NULL shift");
+  if (!finite_pos(rho) || !std::isfinite(alpha) || alpha < 0.0)
+    return fail(LAMINO_E_INVALID, "lamino_tv_shrink: need rho > 0 and alpha >= 0 (finite)");
+  hipError_t e = lam::tv_shrink(d_vol, d_lambda, d_shift, d_psi, (float)alpha, (float)rho, nz, ny,
+                                nx, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_tv_shrink");
+}
+
+int lamino_admm_tv_state_bytes(const lamino_plan_t* p, size_t* bytes) {
+  if (!p || !bytes) return fail(LAMINO_E_INVALID, "lamino_admm_tv_state_bytes: NULL argument");
+  if (!lam::tv_dims_ok(p->nz, p->n, p->n))
+    return fail(LAMINO_E_UNSUPPORTED, "lamino_admm_tv_state_bytes: volume too large");
+  *bytes = lam::admm_state_bytes(p);
+  return LAMINO_OK;
+}
+
+int lamino_admm_tv(const lamino_plan_t* p, const float* d_data, float* d_vol, double alpha,
+                   double rho, int outer, int inner, int resume, void* d_state, void* stream) {
+  const int c = check_call(p, d_data, d_vol, "lamino_admm_tv");
+  if (c) return c;
+  if (!d_state) return fail(LAMINO_E_INVALID, "lamino_admm_tv: NULL state");
+  if ((uintptr_t)d_state & 255)
+    return fail(LAMINO_E_INVALID, "lamino_admm_tv: state must be 256-byte aligned");
+  if (p->opts.data_dtype != LAMINO_F32)
+    return fail(LAMINO_E_INVALID, "lamino_admm_tv: the plan's data dtype must be float32");
+  if (!finite_pos(rho) || !std::isfinite(alpha) || alpha < 0.0)
+    return fail(LAMINO_E_INVALID, "lamino_admm_tv: need rho > 0 and alpha >= 0 (finite)");
+  if (outer < 0 || inner < 0)
+    return fail(LAMINO_E_INVALID, "lamino_admm_tv: negative iteration count");
+  if (!lam::tv_dims_ok(p->nz, p->n, p->n))
+    return fail(LAMINO_E_UNSUPPORTED, "lamino_admm_tv: volume too large");
+  hipError_t e = lam::run_admm_tv(p, d_data, d_vol, (float)alpha, (float)rho, outer, inner,
+                                  resume, d_state, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_admm_tv");
+}
+
 int lamino_plan_destroy(lamino_plan_t* p) {
   if (!p) return LAMINO_OK;
   for (auto& m : p->marks) {

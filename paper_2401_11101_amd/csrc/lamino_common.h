@@ -261,6 +261,21 @@ LAM_HD void ring_tile(int rank, int ntx, int& tx, int& ty) {
   }
 }
 
+// Tile of a volume stencil kernel launched on `grid` blocks (a multiple of
+// 8): hardware block b runs on XCD b % 8, so block b takes tile
+// (b % 8) * (grid / 8) + b / 8 and each XCD walks one contiguous run of the
+// nb tiles (x tiles fastest, then y, then z).  Returns false for the
+// padding blocks past nb.
+LAM_HD bool xcd_tile(int b, int grid, int nb, int nbx, int nby, int& bx, int& by, int& bz) {
+  const int t = (b & 7) * (grid >> 3) + (b >> 3);
+  if (t >= nb) return false;
+  bx = t % nbx;
+  const int r = t / nbx;
+  by = r % nby;
+  bz = r / nby;
+  return true;
+}
+
 // Wrap an integer grid coordinate to [-N/2, N/2) (N a power of two).
 LAM_HD int wrap_centred(int k, int N) { return ((k + (N >> 1)) & (N - 1)) - (N >> 1); }
 

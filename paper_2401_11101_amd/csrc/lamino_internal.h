@@ -96,4 +96,16 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
 hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        hipStream_t s);
 
+// Total-variation operators and the ADMM driver (enqueue only).
+size_t admm_state_bytes(const lamino_plan_s* p);
+bool tv_dims_ok(int nz, int ny, int nx);
+hipError_t tv_grad(const float* mu, float* out, int nz, int ny, int nx, hipStream_t s);
+hipError_t tv_div(const float* p, float* out, int nz, int ny, int nx, hipStream_t s);
+hipError_t tv_term(const float* mu, const float* shift, const float* base, float rho, float* out,
+                   int nz, int ny, int nx, hipStream_t s);
+hipError_t tv_shrink(const float* mu, float* lam, float* shift, float* psi, float alpha, float rho,
+                     int nz, int ny, int nx, hipStream_t s);
+hipError_t run_admm_tv(const lamino_plan_s* p, const float* d_data, float* mu, float alpha,
+                       float rho, int outer, int inner, int resume, void* state, hipStream_t s);
+
 }  // namespace lam

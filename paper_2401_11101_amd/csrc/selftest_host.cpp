@@ -9,6 +9,9 @@
 //          its wrapped base cell, inside that tile's candidate interval
 //          (interpolation).
 //  ring    the centre-out tile order is a bijection onto the ntx x ntx tiles.
+//  xcd     the XCD-grouped tile order of the volume stencil kernels (64 x 4
+//          x 16 voxel tiles) covers every voxel of ragged volumes exactly
+//          once, and each XCD's tiles form one contiguous run.
 // Prints one line per check and exits non-zero on the first failure.
 #include <algorithm>
 #include <cmath>
@@ -170,9 +173,52 @@ static int check_ring_order() {
   return 0;
 }
 
+static int check_xcd_tiles() {
+  const int shapes[][3] = {{1, 1, 1}, {16, 4, 64}, {7, 9, 130}, {33, 65, 65}, {256, 256, 256},
+                           {17, 3, 200}, {512, 1024, 1024}};
+  for (const auto& sh : shapes) {
+    const int nz = sh[0], ny = sh[1], nx = sh[2];
+    const int nbx = (nx + 63) / 64, nby = (ny + 3) / 4, nbz = (nz + 15) / 16;
+    const int nb = nbx * nby * nbz, grid = 8 * ((nb + 7) / 8);
+    std::vector<unsigned char> seen((size_t)nb, 0);
+    std::vector<int> first(8, -1), last(8, -1);
+    size_t voxels = 0;
+    for (int b = 0; b < grid; ++b) {
+      int bx, by, bz;
+      if (!xcd_tile(b, grid, nb, nbx, nby, bx, by, bz)) continue;
+      if (bx < 0 || bx >= nbx || by < 0 || by >= nby || bz < 0 || bz >= nbz) {
+        std::printf("xcd %dx%dx%d block %d out of range FAIL\n", nz, ny, nx, b);
+        return 1;
+      }
+      const int t = (bz * nby + by) * nbx + bx;
+      if (seen[t]++) {
+        std::printf("xcd %dx%dx%d tile %d twice FAIL\n", nz, ny, nx, t);
+        return 1;
+      }
+      // each XCD's successive blocks take successive tiles
+      const int x = b & 7;
+      if (last[x] >= 0 && t != last[x] + 1) {
+        std::printf("xcd %dx%dx%d XCD %d not contiguous FAIL\n", nz, ny, nx, x);
+        return 1;
+      }
+      if (first[x] < 0) first[x] = t;
+      last[x] = t;
+      voxels += (size_t)std::min(64, nx - bx * 64) * std::min(4, ny - by * 4) *
+                std::min(16, nz - bz * 16);
+    }
+    if (voxels != (size_t)nx * ny * nz) {
+      std::printf("xcd %dx%dx%d covers %zu voxels FAIL\n", nz, ny, nx, voxels);
+      return 1;
+    }
+  }
+  std::printf("xcd ok\n");
+  return 0;
+}
+
 int main() {
   if (check_fft()) return 1;
   if (check_candidates()) return 1;
   if (check_ring_order()) return 1;
+  if (check_xcd_tiles()) return 1;
   return 0;
 }

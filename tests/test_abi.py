@@ -123,4 +123,51 @@ def test_calls_before_bind_fail_cleanly(lib):
 def test_host_index_logic_selftest(lib):
     out = subprocess.run([_build.SELFTEST], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
-    assert "fft ok" in out.stdout and "cand ok" in out.stdout
+    assert "fft ok" in out.stdout and "cand ok" in out.stdout and "xcd ok" in out.stdout
+
+
+def _a256(x):
+    return (x + 255) // 256 * 256
+
+
+def test_admm_state_layout(lib):
+    # lambda [3][nz][n][n] at 0, shift at the next 256-byte boundary, then
+    # w, g, eta, t (volumes), q (data), per-block partials of the volume
+    # and data reductions (1024 blocks) and scalars.
+    for (nz, n, nt, h, w) in [(16, 20, 12, 14, 18), (256, 256, 720, 256, 320), (33, 65, 7, 9, 11)]:
+        plan = _abi.lamino_plan(_geom(nz, n, nt, h, w), _abi.lamino_opts_default())
+        nv = nz * n * n
+        tiles = -(-n // 64) * -(-n // 4) * -(-nz // 16)
+        blocks = 8 * -(-tiles // 8)
+        want = (2 * _a256(3 * nv * 4) + 4 * _a256(nv * 4) + _a256(nt * h * w * 4)
+                + _a256(blocks * 16) + 1024 * 16 + 256)
+        assert _abi.lamino_admm_tv_state_bytes(plan) == want
+        _abi.lamino_plan_destroy(plan)
+
+
+def test_tv_calls_validate_arguments_on_the_host(lib):
+    P = ctypes.c_void_p
+    cases = [
+        (lambda: _abi.lamino_tv_grad(P(None), P(256), 4, 4, 4, None), _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_grad(P(256), P(512), 0, 4, 4, None), _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_div(P(256), P(512), 4, -1, 4, None), _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_term(P(256), P(None), P(None), float("nan"), P(512), 4, 4, 4, None),
+         _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_shrink(P(256), P(512), P(768), P(None), 0.1, 0.0, 4, 4, 4, None),
+         _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_shrink(P(256), P(512), P(768), P(None), -0.1, 1.0, 4, 4, 4, None),
+         _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_shrink(P(256), P(512), P(None), P(None), 0.1, 1.0, 4, 4, 4, None),
+         _abi.LAMINO_E_INVALID),
+        (lambda: _abi.lamino_tv_grad(P(256), P(512), 1 << 30, 1 << 20, 1 << 20, None),
+         _abi.LAMINO_E_UNSUPPORTED),
+    ]
+    for call, code in cases:
+        with pytest.raises(_abi.LaminoError) as e:
+            call()
+        assert e.value.code == code
+    plan = _abi.lamino_plan(_geom(), _abi.lamino_opts_default())
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_admm_tv(plan, P(256), P(512), 0.1, 1.0, 1, 1, 0, P(768), None)
+    assert e.value.code == _abi.LAMINO_E_UNBOUND
+    _abi.lamino_plan_destroy(plan)
