@@ -47,7 +47,9 @@ extern "C" {
 
 typedef struct lamino_plan_s lamino_plan_t;
 
-typedef enum { LAMINO_F32 = 0, LAMINO_F16 = 1, LAMINO_BF16 = 2 } lamino_dtype;
+/* Element types.  LAMINO_U8 (8-bit detector values 0..255, read as floats)
+ * is accepted for input data only: lamino_fwd rejects a plan with U8 data. */
+typedef enum { LAMINO_F32 = 0, LAMINO_F16 = 1, LAMINO_BF16 = 2, LAMINO_U8 = 3 } lamino_dtype;
 
 /* Window of the FBP filter (the paper names ramp, Shepp-Logan, Parzen). */
 typedef enum { LAMINO_RAMP = 0, LAMINO_SHEPP_LOGAN = 1, LAMINO_PARZEN = 2 } lamino_filter;
@@ -73,7 +75,7 @@ typedef struct {
 
 /* Options; zero-initialise and then call lamino_opts_default. */
 typedef struct {
-  int data_dtype;     /* lamino_dtype of d                                    */
+  int data_dtype;     /* lamino_dtype of d (F32, F16, BF16, or U8 for input)   */
   int storage_dtype;  /* lamino_dtype of the stored spectra and slab planes.
                          Accumulation is float32 throughout.  Gridding and
                          the x3 transform multiply on the matrix cores: with
@@ -143,12 +145,41 @@ int lamino_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void
 
 /* Forward projection (eq:fwd via eq:fftfwd): d = L vol.
  * d_vol: device float vol[nz][n][n] (read only); d_data: device
- * d[n_theta][h][w] in data_dtype (written).  Errors as lamino_fbp. */
+ * d[n_theta][h][w] in data_dtype (written; E_INVALID for U8 data).
+ * Errors as lamino_fbp. */
 int lamino_fwd(const lamino_plan_t* plan, const float* d_vol, void* d_data, void* stream);
 
 /* Adjoint (eq:adj via eq:fftadj): vol = L* d, the exact transpose of
  * lamino_fwd.  Arguments as lamino_fbp. */
 int lamino_adj(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Direct discretisation (the O(N^3 N_theta) method the Fourier route
+ * replaces: eq:adj and eq:recon evaluated as line integrals with linear
+ * interpolation).  Voxel-driven bilinear form on the plan's geometry:
+ *   L*_dir d (x) = sum_theta sum_{r,c} d(theta, r, c) hat(u_c - x.e_u) hat(v_r - x.e_v),
+ *   hat(s) = max(0, 1 - |s|), u_c = c - w/2, v_r = r - h/2,
+ * i.e. bilinear interpolation of each projection at (x.e_u, x.e_v) with
+ * detector pixels outside h x w taken as zero.  FBP_dir first filters every
+ * detector row with W(m) (the transfer function of lamino_fbp, including
+ * (pi / n_theta) cos(phi)): rows zero-padded to w_p (column c at index
+ * (c - w/2) mod w_p), w_p-point DFT, multiply, inverse DFT, cropped back to
+ * w.  Arithmetic: float32 with projected coordinates formed in float64. */
+
+/* Bytes of the workspace lamino_direct_fbp needs (the filtered rows:
+ * n_theta * h * w float32, 256-byte multiple).  Host-only. */
+int lamino_direct_work_bytes(const lamino_plan_t* plan, size_t* bytes);
+
+/* vol = L*_dir (filtered d).  d_data: device d[n_theta][h][w] in the plan's
+ * data dtype; d_vol: device float vol[nz][n][n] (written); d_work: device
+ * buffer of lamino_direct_work_bytes bytes, 256-byte aligned (contents
+ * overwritten).  Errors: E_INVALID, E_UNBOUND, E_HIP. */
+int lamino_direct_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* d_work,
+                      void* stream);
+
+/* vol = L*_dir d (no filter).  Arguments as lamino_direct_fbp without the
+ * workspace. */
+int lamino_direct_adj(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
 
 /* Stages reported by lamino_plan_stage_times. */
 enum {

@@ -10,7 +10,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblamino.so")
 
-LAMINO_F32, LAMINO_F16, LAMINO_BF16 = 0, 1, 2
+LAMINO_F32, LAMINO_F16, LAMINO_BF16, LAMINO_U8 = 0, 1, 2, 3
 LAMINO_RAMP, LAMINO_SHEPP_LOGAN, LAMINO_PARZEN = 0, 1, 2
 LAMINO_OK = 0
 LAMINO_E_INVALID = -1
@@ -33,6 +33,9 @@ EXPORTED = (
     "lamino_plan_destroy",
     "lamino_strerror",
     "lamino_last_error",
+    "lamino_direct_work_bytes",
+    "lamino_direct_fbp",
+    "lamino_direct_adj",
     "lamino_tv_grad",
     "lamino_tv_div",
     "lamino_tv_term",
@@ -129,6 +132,9 @@ def load_library(path=LIB_PATH):
     lib.lamino_last_error.argtypes = []
     lib.lamino_last_error.restype = ctypes.c_char_p
     I, D = ctypes.c_int, ctypes.c_double
+    lib.lamino_direct_work_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.lamino_direct_fbp.argtypes = [P, P, P, P, P]
+    lib.lamino_direct_adj.argtypes = [P, P, P, P]
     lib.lamino_tv_grad.argtypes = [P, P, I, I, I, P]
     lib.lamino_tv_div.argtypes = [P, P, I, I, I, P]
     lib.lamino_tv_term.argtypes = [P, P, P, D, P, I, I, I, P]
@@ -138,7 +144,8 @@ def load_library(path=LIB_PATH):
     for name in ("lamino_plan", "lamino_plan_sizes", "lamino_plan_info", "lamino_plan_bind",
                  "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
                  "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
-                 "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink",
+                 "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink", "lamino_direct_work_bytes",
+                 "lamino_direct_fbp", "lamino_direct_adj",
                  "lamino_admm_tv_state_bytes", "lamino_admm_tv"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -189,6 +196,20 @@ def lamino_fwd(plan, d_vol, d_data, stream):
 
 def lamino_adj(plan, d_data, d_vol, stream):
     _check(load_library().lamino_adj(plan, d_data, d_vol, stream), "lamino_adj")
+
+
+def lamino_direct_work_bytes(plan):
+    b = ctypes.c_size_t()
+    _check(load_library().lamino_direct_work_bytes(plan, ctypes.byref(b)), "lamino_direct_work_bytes")
+    return b.value
+
+
+def lamino_direct_fbp(plan, d_data, d_vol, d_work, stream):
+    _check(load_library().lamino_direct_fbp(plan, d_data, d_vol, d_work, stream), "lamino_direct_fbp")
+
+
+def lamino_direct_adj(plan, d_data, d_vol, stream):
+    _check(load_library().lamino_direct_adj(plan, d_data, d_vol, stream), "lamino_direct_adj")
 
 
 def lamino_tv_grad(d_vol, d_grad, nz, ny, nx, stream):

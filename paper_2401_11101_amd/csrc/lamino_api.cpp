@@ -119,6 +119,8 @@ void build_tables(lamino_plan_s* p) {
   p->off_x3a = take((size_t)2 * p->x3a_rows * p->x3a_k * 2);
   p->off_x3f = take((size_t)2 * p->x3f_rows * p->x3f_k * 2);
   p->off_tw = take((size_t)twmax * 8);
+  p->off_trig_d = take((size_t)p->n_theta * 16);
+  p->off_filt_dir = take((size_t)p->w_p * 4);
   p->table_bytes = off;
   p->host_tables.assign(off, 0);
   unsigned char* base = p->host_tables.data();
@@ -184,6 +186,20 @@ void build_tables(lamino_plan_s* p) {
     tw[2 * t] = (float)std::cos(a);
     tw[2 * t + 1] = (float)std::sin(a);
   }
+  // direct path: angles in double precision, row filter W(m) / w_p
+  double* trd = reinterpret_cast<double*>(base + p->off_trig_d);
+  for (int j = 0; j < p->n_theta; ++j) {
+    trd[2 * j] = std::cos(p->theta[j]);
+    trd[2 * j + 1] = std::sin(p->theta[j]);
+  }
+  float* fdir = reinterpret_cast<float*>(base + p->off_filt_dir);
+  for (int k = 0; k < p->w_p; ++k) {
+    const int m = k < p->w_p / 2 ? k : k - p->w_p;
+    const double km = (double)m / p->w_p;
+    fdir[k] = k == p->w_p / 2 ? 0.f
+                              : (float)(M_PI / p->n_theta * cphi * std::fabs(km) *
+                                        window(km, p->opts.filter) / p->w_p);
+  }
 }
 
 }  // namespace
@@ -191,7 +207,7 @@ void build_tables(lamino_plan_s* p) {
 namespace lam {
 
 size_t storage_bytes(int dtype) { return dtype == LAMINO_F32 ? 8 : 4; }
-size_t data_bytes(int dtype) { return dtype == LAMINO_F32 ? 4 : 2; }
+size_t data_bytes(int dtype) { return dtype == LAMINO_F32 ? 4 : (dtype == LAMINO_U8 ? 1 : 2); }
 
 KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   KParams k;
@@ -226,6 +242,10 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.x3f_rows = p->x3f_rows;
   k.x3f_k = p->x3f_k;
   k.tw = reinterpret_cast<const float2*>(t + p->off_tw);
+  k.trig_d = reinterpret_cast<const double2*>(t + p->off_trig_d);
+  k.filt_dir = reinterpret_cast<const float*>(t + p->off_filt_dir);
+  k.sin_phi = std::sin(p->tilt);
+  k.cos_phi = std::cos(p->tilt);
   return k;
 }
 
@@ -316,7 +336,7 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
     return fail(LAMINO_E_UNSUPPORTED, "lamino_plan: n_theta=%d above 65535", geom->n_theta);
   if (!std::isfinite(geom->tilt) || std::fabs(geom->tilt) >= M_PI / 2)
     return fail(LAMINO_E_INVALID, "lamino_plan: tilt must be finite with |tilt| < pi/2");
-  if (o.data_dtype < 0 || o.data_dtype > 2 || o.storage_dtype < 0 || o.storage_dtype > 2)
+  if (o.data_dtype < 0 || o.data_dtype > 3 || o.storage_dtype < 0 || o.storage_dtype > 2)
     return fail(LAMINO_E_INVALID, "lamino_plan: unknown dtype");
   if (o.filter < 0 || o.filter > 2) return fail(LAMINO_E_INVALID, "lamino_plan: unknown filter");
   if (o.pad_u == 0.0) o.pad_u = 2.0;
@@ -470,8 +490,34 @@ int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* s
 int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* stream) {
   const int c = check_call(p, d_vol, d_data, "lamino_fwd");
   if (c) return c;
+  if (p->opts.data_dtype == LAMINO_U8)
+    return fail(LAMINO_E_INVALID, "lamino_fwd: 8-bit data is accepted as input only");
   hipError_t e = lam::run_forward(p, d_vol, d_data, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fwd");
+}
+
+int lamino_direct_work_bytes(const lamino_plan_t* p, size_t* bytes) {
+  if (!p || !bytes) return fail(LAMINO_E_INVALID, "lamino_direct_work_bytes: NULL argument");
+  *bytes = lam::direct_work_bytes(p);
+  return LAMINO_OK;
+}
+
+int lamino_direct_fbp(const lamino_plan_t* p, const void* d_data, float* d_vol, void* d_work,
+                      void* stream) {
+  const int c = check_call(p, d_data, d_vol, "lamino_direct_fbp");
+  if (c) return c;
+  if (!d_work) return fail(LAMINO_E_INVALID, "lamino_direct_fbp: NULL workspace");
+  if ((uintptr_t)d_work & 255)
+    return fail(LAMINO_E_INVALID, "lamino_direct_fbp: workspace must be 256-byte aligned");
+  hipError_t e = lam::run_direct(p, d_data, d_vol, d_work, true, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_direct_fbp");
+}
+
+int lamino_direct_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {
+  const int c = check_call(p, d_data, d_vol, "lamino_direct_adj");
+  if (c) return c;
+  hipError_t e = lam::run_direct(p, d_data, d_vol, nullptr, false, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_direct_adj");
 }
 
 static int check_tv(const void* a, const void* b, int nz, int ny, int nx, const char* who) {

@@ -33,6 +33,10 @@ struct KParams {
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
   float x3_out_scale;     // 1 / (power-of-two factor carried by the stored spectra)
   const float2* tw;       // [2^log2_twmax] exp(-2 pi i t / 2^log2_twmax)
+  // direct (line-integral) path
+  const double2* trig_d;  // [n_theta] (cos, sin) in double precision
+  const float* filt_dir;  // [w_p] W(m) / w_p of the row filter, index k = m mod w_p
+  double sin_phi, cos_phi;
 };
 
 }  // namespace lam
@@ -49,6 +53,7 @@ struct lamino_plan_s {
   int z_chunk, slab_chunk, theta_chunk;
   // table layout (bytes)
   size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_x3a, off_x3f, off_tw;
+  size_t off_trig_d, off_filt_dir;
   double spectra_scale;  // power of two folded into the filter tables
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
   size_t table_bytes;
@@ -95,6 +100,12 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
                               bool fbp_filter, hipStream_t s);
 hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        hipStream_t s);
+
+// Direct line-integral backprojection (enqueue only); d_work holds the
+// filtered rows when fbp_filter is set.
+size_t direct_work_bytes(const lamino_plan_s* p);
+hipError_t run_direct(const lamino_plan_s* p, const void* d_data, float* d_vol, void* d_work,
+                      bool fbp_filter, hipStream_t s);
 
 // Total-variation operators and the ADMM driver (enqueue only).
 size_t admm_state_bytes(const lamino_plan_s* p);

@@ -11,7 +11,7 @@ import torch
 from . import _abi
 
 _DTYPES = {"f32": (_abi.LAMINO_F32, torch.float32), "f16": (_abi.LAMINO_F16, torch.float16),
-           "bf16": (_abi.LAMINO_BF16, torch.bfloat16)}
+           "bf16": (_abi.LAMINO_BF16, torch.bfloat16), "u8": (_abi.LAMINO_U8, torch.uint8)}
 _FILTERS = {"ramp": _abi.LAMINO_RAMP, "shepp-logan": _abi.LAMINO_SHEPP_LOGAN,
             "parzen": _abi.LAMINO_PARZEN}
 
@@ -108,6 +108,28 @@ class Plan:
         self._check(out, self.shape_data, self.torch_data_dtype, "out")
         _abi.lamino_fwd(self._h, ctypes.c_void_p(vol.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                         _stream_handle(stream))
+        return out
+
+    def direct_fbp(self, data, out=None, stream=None):
+        """FBP by the direct line-integral discretisation (O(N^3 n_theta)):
+        rows filtered with the same W(m), then bilinear backprojection."""
+        self._check(data, self.shape_data, self.torch_data_dtype, "data")
+        out = torch.empty(self.shape_vol, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(out, self.shape_vol, torch.float32, "out")
+        if getattr(self, "_direct_work", None) is None:
+            nbytes = _abi.lamino_direct_work_bytes(self._h)
+            self._direct_work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _abi.lamino_direct_fbp(self._h, ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               ctypes.c_void_p(self._direct_work.data_ptr()), _stream_handle(stream))
+        return out
+
+    def direct_adj(self, data, out=None, stream=None):
+        """Direct bilinear backprojection L*_dir d (no filter)."""
+        self._check(data, self.shape_data, self.torch_data_dtype, "data")
+        out = torch.empty(self.shape_vol, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(out, self.shape_vol, torch.float32, "out")
+        _abi.lamino_direct_adj(self._h, ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                               _stream_handle(stream))
         return out
 
     def profile(self, enable=True):
