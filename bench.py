@@ -333,6 +333,71 @@ def admm_tv_reconstruction(dev, outer=4, inner=4):
             "tv_kernels": krep}
 
 
+def table1(dev, sizes=(256, 512, 1024, 2048)):
+    """The paper's timing-table workload: N projections of N x N, 8-bit data,
+    tilt 20 deg, N^3 volume (float32).  Fourier-route FBP (fp32 and fp16
+    storage) against the direct line-integral FBP, device-resident, one timed
+    run each after a warm-up; plus a PCIe-inclusive run at N = 1024."""
+    from paper_2401_11101_amd import Plan
+
+    tilt = np.deg2rad(20.0)
+    stream = torch.cuda.current_stream()
+    rows = []
+    e2e = None
+    for N in sizes:
+        log(f"table1: N = {N}")
+        ells = synth.random_ellipsoids(20, N, N, seed=0)
+        d = synth.project_ellipsoids(ells, N, N, N, tilt, device=dev, dtype=torch.float32, theta_chunk=8)
+        d8 = torch.clamp(d * (255.0 / float(d.max())), 0, 255).round().to(torch.uint8)
+        del d
+        torch.cuda.empty_cache()
+        vol = torch.empty((N, N, N), dtype=torch.float32, device=dev)
+        row = {"N": N}
+        # float32 storage needs ~2x the fp16 workspace: skipped above N = 1536
+        if N <= 1536:
+            plan = Plan(N, N, N, N, N, tilt, data_dtype="u8", storage_dtype="f32")
+            row["fourier_f32_ms"] = round(_event_ms(lambda: plan.fbp(d8, out=vol), 1, stream), 3)
+            del plan
+            torch.cuda.empty_cache()
+        # the direct FBP needs only the plan's tables: it runs on the fp16 plan
+        plan = Plan(N, N, N, N, N, tilt, data_dtype="u8", storage_dtype="f16")
+        row["fourier_f16_ms"] = round(_event_ms(lambda: plan.fbp(d8, out=vol), 1, stream), 3)
+        if N == 1024:
+            e2e = _end_to_end(plan, d8, vol, stream)
+        row["direct_ms"] = round(_event_ms(lambda: plan.direct_fbp(d8, out=vol), 1, stream), 3)
+        row["direct_voxel_angles_per_s"] = float(f"{float(N) ** 4 / (row['direct_ms'] * 1e-3):.4g}")
+        del plan, vol, d8
+        torch.cuda.empty_cache()
+        for storage in ("f32", "f16"):
+            if f"fourier_{storage}_ms" in row:
+                row[f"gain_{storage}"] = round(row["direct_ms"] / row[f"fourier_{storage}_ms"], 3)
+        row["fourier_f16_gvoxel_per_s"] = round(N ** 3 / (row["fourier_f16_ms"] * 1e-3) / 1e9, 4)
+        rows.append(row)
+    return {"workload": "N projections of N x N over [0, 2pi), 8-bit data, tilt 20 deg, N^3 float32 "
+                        "volume, Shepp-Logan; device-resident, one run after a warm-up",
+            "rows": rows, "end_to_end_N1024_f16": e2e,
+            "paper_context": "A100 40 GB, times including the chunked host-device pipeline: Fourier "
+                             "3.0 / 8.6 / 21.1 s and direct 9.3 / 52.1 / 222.1 s at N = 1024 / 1536 / 2048"}
+
+
+def _end_to_end(plan, d8, vol, stream):
+    """Pinned-host 8-bit data -> device, FBP, volume -> pinned host, one run."""
+    h_in = torch.empty(d8.shape, dtype=torch.uint8, pin_memory=True)
+    h_in.copy_(d8.cpu())
+    h_out = torch.empty(vol.shape, dtype=torch.float32, pin_memory=True)
+    dd = torch.empty_like(d8)
+
+    def run():
+        dd.copy_(h_in, non_blocking=True)
+        plan.fbp(dd, out=vol)
+        h_out.copy_(vol, non_blocking=True)
+
+    ms = _event_ms(run, 1, stream)
+    N = vol.shape[0]
+    return {"ms": round(ms, 3), "gvoxel_per_s": round(N ** 3 / (ms * 1e-3) / 1e9, 4),
+            "bytes_h2d": d8.numel(), "bytes_d2h": vol.numel() * 4}
+
+
 def copy_calibration(nbytes=1 << 30):
     """Plain copies of `nbytes` with 4-, 8- and 16-byte lane accesses (and the
     runtime's own device copy), each once: under rocprofv3 --pmc their
@@ -368,6 +433,8 @@ def main():
                     help="also time the 1024^2 x 512 volume, CGLS and the TV-regularised ADMM")
     ap.add_argument("--admm", action="store_true",
                     help="also time the TV-regularised ADMM and its kernels (part of --extra)")
+    ap.add_argument("--table1", action="store_true",
+                    help="also run the Fourier-vs-direct timing table (N = 256 .. 2048, 8-bit data)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -443,6 +510,8 @@ def main():
     if args.extra or args.admm:
         log("timing the TV-regularised ADMM")
         line["admm_tv"] = admm_tv_reconstruction(dev)
+    if args.table1:
+        line["table1"] = table1(dev)
     if not args.no_cpu:
         log("timing the CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(data.double().cpu().numpy())
