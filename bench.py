@@ -93,7 +93,7 @@ def algorithmic_work(info, storage_bytes, data_bytes):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fbp_256cube_400proj_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2401_11101_amd", "csrc", f)
-                  for f in ("lamino_kernels.hip", "lamino_common.h")]
+                  for f in ("lamino_kernels.hip", "lamino_common.h", "lamino_device.h")]
 
 
 def measured_traffic(kernel):
