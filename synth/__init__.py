@@ -13,6 +13,10 @@ Recipe (all draws from numpy's PCG64 with the given seed):
   density     U[0, 1]; densities of overlapping ellipsoids add
   noise       i.i.d. N(0, (p * rms(d))^2), its own seed
   speckle     d * exp(a Z - a^2 / 2), Z ~ N(0, 1) per pixel (log-normal)
+  raw counts  detector images of line integrals d under the recording model
+              raw = exp(-d) (flat - dark) + dark: dark ~ dark_level (1 + 0.05 Z),
+              flat ~ flat_level (1 + 0.05 Z) per pixel, Poisson-like noise
+              sqrt(raw) Z, rounded and clipped to the integer type
 
 Projections are exact chord lengths along the rays of the scan: the ray
 hitting detector pixel (u, v) at angle theta is u e_u + v e_v + t b with
@@ -113,3 +117,19 @@ def apply_speckle(d, amp, seed=1):
 def random_array(shape, seed, dtype=np.float64):
     """Standard-normal test array."""
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)
+
+
+def raw_counts(d, dark_level=100.0, flat_level=4.0e4, seed=5, dtype=np.uint16):
+    """Seeded raw detector counts for line integrals d[n_theta][h][w]
+    (numpy float64): returns (raw, dark, flat) with dark and flat as
+    float32 [h][w] images and raw as the integer dtype."""
+    d = np.asarray(d, dtype=np.float64)
+    rng = np.random.default_rng(seed)
+    h, w = d.shape[-2:]
+    dark = dark_level * (1.0 + 0.05 * rng.standard_normal((h, w)))
+    flat = flat_level * (1.0 + 0.05 * rng.standard_normal((h, w)))
+    ideal = np.exp(-d) * (flat - dark) + dark
+    noisy = ideal + np.sqrt(np.maximum(ideal, 0.0)) * rng.standard_normal(d.shape)
+    top = np.iinfo(dtype).max
+    raw = np.clip(np.rint(noisy), 0, top).astype(dtype)
+    return raw, dark.astype(np.float32), flat.astype(np.float32)
