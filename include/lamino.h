@@ -47,9 +47,16 @@ extern "C" {
 
 typedef struct lamino_plan_s lamino_plan_t;
 
-/* Element types.  LAMINO_U8 (8-bit detector values 0..255, read as floats)
- * is accepted for input data only: lamino_fwd rejects a plan with U8 data. */
-typedef enum { LAMINO_F32 = 0, LAMINO_F16 = 1, LAMINO_BF16 = 2, LAMINO_U8 = 3 } lamino_dtype;
+/* Element types.  LAMINO_U8 and LAMINO_U16 (8- and 16-bit detector values,
+ * read as floats) are accepted for input data only: lamino_fwd rejects a
+ * plan with integer data. */
+typedef enum {
+  LAMINO_F32 = 0,
+  LAMINO_F16 = 1,
+  LAMINO_BF16 = 2,
+  LAMINO_U8 = 3,
+  LAMINO_U16 = 4
+} lamino_dtype;
 
 /* Window of the FBP filter (the paper names ramp, Shepp-Logan, Parzen). */
 typedef enum { LAMINO_RAMP = 0, LAMINO_SHEPP_LOGAN = 1, LAMINO_PARZEN = 2 } lamino_filter;
@@ -75,7 +82,7 @@ typedef struct {
 
 /* Options; zero-initialise and then call lamino_opts_default. */
 typedef struct {
-  int data_dtype;     /* lamino_dtype of d (F32, F16, BF16, or U8 for input)   */
+  int data_dtype;     /* lamino_dtype of d (F32, F16, BF16; U8, U16 input only) */
   int storage_dtype;  /* lamino_dtype of the stored spectra and slab planes.
                          Accumulation is float32 throughout.  Gridding and
                          the x3 transform multiply on the matrix cores: with
@@ -143,9 +150,22 @@ int lamino_plan_bind(lamino_plan_t* plan, void* d_tables, void* d_work, void* st
  * E_UNBOUND, E_HIP. */
 int lamino_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
 
+/* Filtered backprojection of raw detector counts.  The recording model of
+ * Section "Laminography reconstruction" (the paragraph after eq:fwd),
+ * raw = exp(-d) (flat - dark) + dark, is inverted inside the first detector
+ * kernel while it stages the data:
+ *   d = -log(max(ratio, min_ratio)),  ratio = (raw - dark) / (flat - dark),
+ * with ratio = min_ratio where flat - dark <= 0 (dead pixels); then as
+ * lamino_fbp.  d_raw: device [n_theta][h][w] in the plan's data dtype
+ * (typically U16 or U8); d_dark, d_flat: device float32 [h][w] (averaged
+ * dark- and flat-field images); min_ratio > 0 (E_INVALID otherwise).
+ * The corrected data are never written to memory.  Errors as lamino_fbp. */
+int lamino_fbp_raw(const lamino_plan_t* plan, const void* d_raw, const float* d_dark,
+                   const float* d_flat, double min_ratio, float* d_vol, void* stream);
+
 /* Forward projection (eq:fwd via eq:fftfwd): d = L vol.
  * d_vol: device float vol[nz][n][n] (read only); d_data: device
- * d[n_theta][h][w] in data_dtype (written; E_INVALID for U8 data).
+ * d[n_theta][h][w] in data_dtype (written; E_INVALID for integer data).
  * Errors as lamino_fbp. */
 int lamino_fwd(const lamino_plan_t* plan, const float* d_vol, void* d_data, void* stream);
 

@@ -10,7 +10,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblamino.so")
 
-LAMINO_F32, LAMINO_F16, LAMINO_BF16, LAMINO_U8 = 0, 1, 2, 3
+LAMINO_F32, LAMINO_F16, LAMINO_BF16, LAMINO_U8, LAMINO_U16 = 0, 1, 2, 3, 4
 LAMINO_RAMP, LAMINO_SHEPP_LOGAN, LAMINO_PARZEN = 0, 1, 2
 LAMINO_OK = 0
 LAMINO_E_INVALID = -1
@@ -26,6 +26,7 @@ EXPORTED = (
     "lamino_plan_info",
     "lamino_plan_bind",
     "lamino_fbp",
+    "lamino_fbp_raw",
     "lamino_fwd",
     "lamino_adj",
     "lamino_plan_profile",
@@ -132,6 +133,7 @@ def load_library(path=LIB_PATH):
     lib.lamino_last_error.argtypes = []
     lib.lamino_last_error.restype = ctypes.c_char_p
     I, D = ctypes.c_int, ctypes.c_double
+    lib.lamino_fbp_raw.argtypes = [P, P, P, P, D, P, P]
     lib.lamino_direct_work_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.lamino_direct_fbp.argtypes = [P, P, P, P, P]
     lib.lamino_direct_adj.argtypes = [P, P, P, P]
@@ -145,7 +147,7 @@ def load_library(path=LIB_PATH):
                  "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
                  "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
                  "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink", "lamino_direct_work_bytes",
-                 "lamino_direct_fbp", "lamino_direct_adj",
+                 "lamino_direct_fbp", "lamino_direct_adj", "lamino_fbp_raw",
                  "lamino_admm_tv_state_bytes", "lamino_admm_tv"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -188,6 +190,11 @@ def lamino_plan_bind(plan, d_tables, d_work, stream):
 
 def lamino_fbp(plan, d_data, d_vol, stream):
     _check(load_library().lamino_fbp(plan, d_data, d_vol, stream), "lamino_fbp")
+
+
+def lamino_fbp_raw(plan, d_raw, d_dark, d_flat, min_ratio, d_vol, stream):
+    _check(load_library().lamino_fbp_raw(plan, d_raw, d_dark, d_flat, float(min_ratio), d_vol, stream),
+           "lamino_fbp_raw")
 
 
 def lamino_fwd(plan, d_vol, d_data, stream):

@@ -208,6 +208,7 @@ namespace lam {
 
 size_t storage_bytes(int dtype) { return dtype == LAMINO_F32 ? 8 : 4; }
 size_t data_bytes(int dtype) { return dtype == LAMINO_F32 ? 4 : (dtype == LAMINO_U8 ? 1 : 2); }
+bool integer_dtype(int dtype) { return dtype == LAMINO_U8 || dtype == LAMINO_U16; }
 
 KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   KParams k;
@@ -246,6 +247,9 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.filt_dir = reinterpret_cast<const float*>(t + p->off_filt_dir);
   k.sin_phi = std::sin(p->tilt);
   k.cos_phi = std::cos(p->tilt);
+  k.dark = nullptr;
+  k.flat = nullptr;
+  k.min_ratio = 0.f;
   return k;
 }
 
@@ -336,7 +340,7 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
     return fail(LAMINO_E_UNSUPPORTED, "lamino_plan: n_theta=%d above 65535", geom->n_theta);
   if (!std::isfinite(geom->tilt) || std::fabs(geom->tilt) >= M_PI / 2)
     return fail(LAMINO_E_INVALID, "lamino_plan: tilt must be finite with |tilt| < pi/2");
-  if (o.data_dtype < 0 || o.data_dtype > 3 || o.storage_dtype < 0 || o.storage_dtype > 2)
+  if (o.data_dtype < 0 || o.data_dtype > 4 || o.storage_dtype < 0 || o.storage_dtype > 2)
     return fail(LAMINO_E_INVALID, "lamino_plan: unknown dtype");
   if (o.filter < 0 || o.filter > 2) return fail(LAMINO_E_INVALID, "lamino_plan: unknown filter");
   if (o.pad_u == 0.0) o.pad_u = 2.0;
@@ -480,6 +484,18 @@ int lamino_fbp(const lamino_plan_t* p, const void* d_data, float* d_vol, void* s
   return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp");
 }
 
+int lamino_fbp_raw(const lamino_plan_t* p, const void* d_raw, const float* d_dark,
+                   const float* d_flat, double min_ratio, float* d_vol, void* stream) {
+  const int c = check_call(p, d_raw, d_vol, "lamino_fbp_raw");
+  if (c) return c;
+  if (!d_dark || !d_flat) return fail(LAMINO_E_INVALID, "lamino_fbp_raw: NULL dark or flat field");
+  if (!std::isfinite(min_ratio) || !(min_ratio > 0.0) || (float)min_ratio <= 0.f)
+    return fail(LAMINO_E_INVALID, "lamino_fbp_raw: min_ratio must be a positive float");
+  hipError_t e = lam::run_backprojection(p, d_raw, d_vol, true, static_cast<hipStream_t>(stream),
+                                         d_dark, d_flat, (float)min_ratio);
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp_raw");
+}
+
 int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {
   const int c = check_call(p, d_data, d_vol, "lamino_adj");
   if (c) return c;
@@ -490,8 +506,8 @@ int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* s
 int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* stream) {
   const int c = check_call(p, d_vol, d_data, "lamino_fwd");
   if (c) return c;
-  if (p->opts.data_dtype == LAMINO_U8)
-    return fail(LAMINO_E_INVALID, "lamino_fwd: 8-bit data is accepted as input only");
+  if (lam::integer_dtype(p->opts.data_dtype))
+    return fail(LAMINO_E_INVALID, "lamino_fwd: integer data is accepted as input only");
   hipError_t e = lam::run_forward(p, d_vol, d_data, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fwd");
 }

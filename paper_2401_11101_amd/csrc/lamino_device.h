@@ -29,6 +29,7 @@ __device__ __forceinline__ void st_c(void* p, size_t i, float2 v, int dt) {
 __device__ __forceinline__ float ld_r(const void* p, size_t i, int dt) {
   if (dt == LAMINO_F32) return reinterpret_cast<const float*>(p)[i];
   if (dt == LAMINO_U8) return (float)reinterpret_cast<const unsigned char*>(p)[i];
+  if (dt == LAMINO_U16) return (float)reinterpret_cast<const unsigned short*>(p)[i];
   if (dt == LAMINO_F16) return __half2float(reinterpret_cast<const __half*>(p)[i]);
   return __bfloat162float(reinterpret_cast<const __hip_bfloat16*>(p)[i]);
 }
@@ -36,6 +37,15 @@ __device__ __forceinline__ void st_r(void* p, size_t i, float v, int dt) {
   if (dt == LAMINO_F32) reinterpret_cast<float*>(p)[i] = v;
   else if (dt == LAMINO_F16) reinterpret_cast<__half*>(p)[i] = __float2half_rn(v);
   else reinterpret_cast<__hip_bfloat16*>(p)[i] = __float2bfloat16(v);
+}
+
+// Line integral from raw counts (recording model raw = exp(-d)(flat - dark)
+// + dark): -log of the flat/dark-corrected ratio, clamped below at min_ratio;
+// a pixel with flat <= dark takes min_ratio.
+__device__ __forceinline__ float flat_dark_log(float raw, float dark, float flat, float min_ratio) {
+  const float den = flat - dark;
+  const float ratio = den > 0.f ? (raw - dark) / den : min_ratio;
+  return -logf(fmaxf(ratio, min_ratio));
 }
 
 // ------------------------------------------------------------ block FFT

@@ -77,6 +77,8 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
   else if constexpr (DT == LAMINO_U8)
     return (float)__builtin_amdgcn_raw_buffer_load_b8(r, byte_off, 0, 0);
+  else if constexpr (DT == LAMINO_U16)
+    return (float)__builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0);
   else if constexpr (DT == LAMINO_F16)
     return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, byte_off, 0, 0)));
   else
@@ -237,6 +239,9 @@ hipError_t run_direct(const lamino_plan_s* p, const void* d_data, float* d_vol, 
                        nbx, nby, nb, grid);
   else if (dt == LAMINO_BF16)
     hipLaunchKernelGGL(k_dir_backproject<LAMINO_BF16>, dim3(grid), dim3(DB_NT), 0, s, kp, src, d_vol,
+                       nbx, nby, nb, grid);
+  else if (dt == LAMINO_U16)
+    hipLaunchKernelGGL(k_dir_backproject<LAMINO_U16>, dim3(grid), dim3(DB_NT), 0, s, kp, src, d_vol,
                        nbx, nby, nb, grid);
   else
     hipLaunchKernelGGL(k_dir_backproject<LAMINO_U8>, dim3(grid), dim3(DB_NT), 0, s, kp, src, d_vol,

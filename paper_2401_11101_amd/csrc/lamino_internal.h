@@ -37,6 +37,10 @@ struct KParams {
   const double2* trig_d;  // [n_theta] (cos, sin) in double precision
   const float* filt_dir;  // [w_p] W(m) / w_p of the row filter, index k = m mod w_p
   double sin_phi, cos_phi;
+  // raw-count prologue of the first detector kernel (dark == NULL: none)
+  const float* dark;      // [h][w]
+  const float* flat;      // [h][w]
+  float min_ratio;
 };
 
 }  // namespace lam
@@ -84,6 +88,7 @@ namespace lam {
 KParams make_params(const lamino_plan_s* p, bool fbp_filter);
 size_t storage_bytes(int dtype);  // bytes of one stored complex value
 size_t data_bytes(int dtype);     // bytes of one real data value
+bool integer_dtype(int dtype);    // U8 / U16: input-only data types
 
 // Stage bracketing (no-ops unless profiling is on).
 struct StageTimer {
@@ -97,7 +102,8 @@ struct StageTimer {
 
 // The three operator pipelines (enqueue only).
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
-                              bool fbp_filter, hipStream_t s);
+                              bool fbp_filter, hipStream_t s, const float* dark = nullptr,
+                              const float* flat = nullptr, float min_ratio = 0.f);
 hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        hipStream_t s);
 

@@ -53,7 +53,11 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
       p.h * wide,
       [&](int e) {
         const int r = e / wide, c = c0 + e - r * wide;
-        return c < p.w ? ld_r(data, (row0 + r) * p.w + c, p.data_dtype) : 0.f;
+        if (c >= p.w) return 0.f;
+        const float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
+        if (!p.dark) return v;
+        const size_t q = (size_t)r * p.w + c;
+        return flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
       },
       [&](int e, float v) {
         const int r = e / wide, cl = e - r * wide;
@@ -914,8 +918,12 @@ static inline char* wptr(const lamino_plan_s* p, size_t off) {
 }
 
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
-                              bool fbp_filter, hipStream_t s) {
-  const KParams kp = make_params(p, fbp_filter);
+                              bool fbp_filter, hipStream_t s, const float* dark, const float* flat,
+                              float min_ratio) {
+  KParams kp = make_params(p, fbp_filter);
+  kp.dark = dark;
+  kp.flat = flat;
+  kp.min_ratio = min_ratio;
   float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
   void* D = wptr(p, p->off_D);
   float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));

@@ -11,7 +11,8 @@ import torch
 from . import _abi
 
 _DTYPES = {"f32": (_abi.LAMINO_F32, torch.float32), "f16": (_abi.LAMINO_F16, torch.float16),
-           "bf16": (_abi.LAMINO_BF16, torch.bfloat16), "u8": (_abi.LAMINO_U8, torch.uint8)}
+           "bf16": (_abi.LAMINO_BF16, torch.bfloat16), "u8": (_abi.LAMINO_U8, torch.uint8),
+           "u16": (_abi.LAMINO_U16, torch.uint16)}
 _FILTERS = {"ramp": _abi.LAMINO_RAMP, "shepp-logan": _abi.LAMINO_SHEPP_LOGAN,
             "parzen": _abi.LAMINO_PARZEN}
 
@@ -90,6 +91,20 @@ class Plan:
         self._check(out, self.shape_vol, torch.float32, "out")
         _abi.lamino_fbp(self._h, ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                         _stream_handle(stream))
+        return out
+
+    def fbp_raw(self, raw, dark, flat, min_ratio=1e-6, out=None, stream=None):
+        """FBP of raw detector counts: -log of the dark/flat-corrected ratio
+        (clamped below at min_ratio) is taken inside the first kernel."""
+        self._check(raw, self.shape_data, self.torch_data_dtype, "raw")
+        field = self.shape_data[1:]
+        self._check(dark, field, torch.float32, "dark")
+        self._check(flat, field, torch.float32, "flat")
+        out = torch.empty(self.shape_vol, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(out, self.shape_vol, torch.float32, "out")
+        _abi.lamino_fbp_raw(self._h, ctypes.c_void_p(raw.data_ptr()), ctypes.c_void_p(dark.data_ptr()),
+                            ctypes.c_void_p(flat.data_ptr()), min_ratio, ctypes.c_void_p(out.data_ptr()),
+                            _stream_handle(stream))
         return out
 
     def adj(self, data, out=None, stream=None):

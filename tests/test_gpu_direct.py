@@ -77,6 +77,9 @@ def test_direct_nonuniform_angles_and_narrow_data_types():
         e = _maxrel(out, ref)
         print(f"  {dt}: max rel {e:.2e}")
         assert e < TOL_DIR
+    plan = Plan(nz, n, nt, h, w, np.deg2rad(tilt), theta=theta, data_dtype="u16")
+    out = to_np(plan.direct_adj(torch.from_numpy(counts.astype(np.uint16)).to(dev())))
+    assert _maxrel(out, ref) < TOL_DIR
     plan = Plan(nz, n, nt, h, w, np.deg2rad(tilt), theta=theta, data_dtype="u8")
     out = to_np(plan.direct_fbp(torch.from_numpy(counts).to(dev())))
     assert _maxrel(out, direct.fbp(counts.astype(np.float64), g)) < TOL_DIR_FBP

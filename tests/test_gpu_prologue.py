@@ -1,0 +1,109 @@
+"""Dark/flat correction and -log fused into the first detector kernel
+(lamino_fbp_raw) against oracle O6 followed by the exact Fourier FBP."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import TOL_F32, dev, ellipsoid_data, rel, to_dev, to_np
+from oracle import nudft, prologue
+from paper_2401_11101_amd import Plan
+
+pytestmark = pytest.mark.gpu
+
+NZ, N, NT, H, W = 20, 24, 30, 20, 28
+PHI = np.deg2rad(30)
+
+
+def _raw(dtype=np.uint16, flat_level=4.0e4, seed=5):
+    g, _, d = ellipsoid_data(10, NZ, N, NT, H, W, PHI, 0.0, seed=1)
+    d = 0.1 * d  # attenuation of O(1) along the longest chords
+    raw, dark, flat = synth.raw_counts(d, flat_level=flat_level, seed=seed, dtype=dtype)
+    return g, raw, dark, flat
+
+
+def _dev_int(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+@pytest.mark.parametrize("dt, np_dt, flat_level", [("u16", np.uint16, 4.0e4), ("u8", np.uint8, 200.0)])
+def test_fbp_raw_matches_oracle(dt, np_dt, flat_level):
+    print(f"fbp_raw {dt}", flush=True)
+    g, raw, dark, flat = _raw(np_dt, flat_level)
+    plan = Plan(NZ, N, NT, H, W, PHI, data_dtype=dt)
+    out = to_np(plan.fbp_raw(_dev_int(raw), to_dev(dark), to_dev(flat), min_ratio=1e-6))
+    dc = prologue.flat_dark_log(raw, dark.astype(np.float64), flat.astype(np.float64), 1e-6)
+    ref = nudft.fbp(dc, g)
+    e = rel(out, ref)
+    print(f"  rel-L2 vs oracle {e:.2e}")
+    assert e < TOL_F32
+
+
+def test_prologue_alone_matches_oracle():
+    # the same kernels on the oracle-corrected data (rounded to float32):
+    # the only difference is the prologue's float32 arithmetic
+    g, raw, dark, flat = _raw()
+    dc = prologue.flat_dark_log(raw, dark, flat, 1e-6).astype(np.float32)
+    p16 = Plan(NZ, N, NT, H, W, PHI, data_dtype="u16")
+    p32 = Plan(NZ, N, NT, H, W, PHI)
+    a = to_np(p16.fbp_raw(_dev_int(raw), to_dev(dark), to_dev(flat)))
+    b = to_np(p32.fbp(to_dev(dc)))
+    e = float(np.abs(a - b).max() / np.abs(b).max())
+    print(f"  max rel vs fbp(oracle prologue) {e:.2e}")
+    assert e < 2e-6
+
+
+def test_clamped_and_dead_pixels():
+    g, raw, dark, flat = _raw()
+    raw = raw.copy()
+    flat = flat.copy()
+    rng = np.random.default_rng(9)
+    idx = rng.integers(0, raw.size, 200)
+    raw.flat[idx] = 0                       # below the dark level: ratio clamped
+    flat[3, 5] = dark[3, 5] - 1.0           # dead pixel: flat below dark
+    flat[7, 2] = dark[7, 2]                 # and flat equal to dark
+    plan = Plan(NZ, N, NT, H, W, PHI, data_dtype="u16")
+    out = to_np(plan.fbp_raw(_dev_int(raw), to_dev(dark), to_dev(flat), min_ratio=1e-3))
+    dc = prologue.flat_dark_log(raw, dark, flat, 1e-3)
+    e = rel(out, nudft.fbp(dc, g))
+    print(f"  rel-L2 with clamped pixels {e:.2e}")
+    assert e < TOL_F32
+
+
+def test_fbp_raw_rejects_bad_arguments():
+    from paper_2401_11101_amd import _abi
+    import ctypes
+    plan = Plan(NZ, N, NT, H, W, PHI, data_dtype="u16")
+    raw = torch.zeros(plan.shape_data, dtype=torch.uint16, device=dev())
+    f = torch.ones((H, W), device=dev())
+    vol = torch.empty(plan.shape_vol, device=dev())
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    for mr in (0.0, -1.0, float("nan"), 1e-60):
+        with pytest.raises(_abi.LaminoError) as e:
+            _abi.lamino_fbp_raw(plan._h, P(raw), P(f), P(f), mr, P(vol), None)
+        assert e.value.code == _abi.LAMINO_E_INVALID
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_raw(plan._h, P(raw), ctypes.c_void_p(None), P(f), 1e-6, P(vol), None)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+
+
+def test_full_size_prologue_equals_corrected_fbp():
+    # 256^3 / 400 projections 256 x 256, tilt 25 deg, 16-bit counts: the
+    # fused prologue against the FBP of the oracle-corrected data
+    nz = n = h = w = 256
+    nt = 400
+    tilt = np.deg2rad(25.0)
+    print("fbp_raw 256^3", flush=True)
+    ells = synth.random_ellipsoids(50, nz, n, seed=0)
+    d = synth.project_ellipsoids(ells, nt, h, w, tilt, device=dev(), dtype=torch.float64)
+    d = (0.02 * d).cpu().numpy()
+    raw, dark, flat = synth.raw_counts(d, seed=3)
+    dc = prologue.flat_dark_log(raw, dark, flat, 1e-6).astype(np.float32)
+    p16 = Plan(nz, n, nt, h, w, tilt, data_dtype="u16")
+    a = p16.fbp_raw(_dev_int(raw), to_dev(dark), to_dev(flat))
+    del p16
+    p32 = Plan(nz, n, nt, h, w, tilt)
+    b = p32.fbp(to_dev(dc))
+    e = float((a - b).abs().max() / b.abs().max())
+    print(f"  max rel {e:.2e}")
+    assert e < 2e-6
