@@ -19,6 +19,7 @@ direct    O1: the direct line-integral discretisation with linear
 cg        O4: conjugate gradients for the least-squares problem
           (Dai-Yuan direction + exact line search, and textbook CGLS)
 prologue  O6: dark/flat field correction and negative logarithm of raw counts
+search    O7: rotation-axis offset (phase ramp on the row spectra) and tilt sweeps
 tv        O5: total-variation regularised reconstruction by ADMM
           (forward-difference gradient, divergence, isotropic soft
           threshold, dual update, CG on the tomography sub-problem)
