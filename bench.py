@@ -398,6 +398,30 @@ def _end_to_end(plan, d8, vol, stream):
             "bytes_h2d": d8.numel(), "bytes_d2h": vol.numel() * 4}
 
 
+def search_sweeps(dev, data):
+    """Axis sweep (41 offsets, -10 .. 10 columns in steps of 0.5) and tilt sweep
+    (21 tilts, 23 .. 27 deg in steps of 0.2) of one slice of the 256^3 workload."""
+    from paper_2401_11101_amd import Plan, search
+
+    stream = torch.cuda.current_stream()
+    plan = Plan(NZ, N, NT, H, W, TILT)
+    shifts = [0.5 * k for k in range(-20, 21)]
+    search.center_sweep(plan, data, shifts[:2], z=NZ // 2)
+    ms_c = _event_ms(lambda: search.center_sweep(plan, data, shifts, z=NZ // 2), 1, stream)
+    del plan
+    tilts = np.deg2rad(23.0 + 0.2 * np.arange(21))
+    t0 = time.perf_counter()
+    search.tilt_sweep(NZ, N, NT, H, W, tilts, data, z=NZ // 2)
+    torch.cuda.synchronize()
+    ms_t = (time.perf_counter() - t0) * 1e3
+    return {"workload": "one slice (z = nz/2) of the 256^3 / 400-projection FBP per candidate",
+            "center_sweep": {"candidates": len(shifts), "ms": round(ms_c, 2),
+                             "ms_per_slice": round(ms_c / len(shifts), 3)},
+            "tilt_sweep": {"candidates": len(tilts), "ms_wall": round(ms_t, 2),
+                           "ms_per_slice": round(ms_t / len(tilts), 3),
+                           "note": "includes the FP64 host tables and their upload for every tilt"}}
+
+
 def copy_calibration(nbytes=1 << 30):
     """Plain copies of `nbytes` with 4-, 8- and 16-byte lane accesses (and the
     runtime's own device copy), each once: under rocprofv3 --pmc their
@@ -435,6 +459,8 @@ def main():
                     help="also time the TV-regularised ADMM and its kernels (part of --extra)")
     ap.add_argument("--table1", action="store_true",
                     help="also run the Fourier-vs-direct timing table (N = 256 .. 2048, 8-bit data)")
+    ap.add_argument("--search", action="store_true",
+                    help="also time the rotation-axis and tilt sweeps (one slice per candidate)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -524,6 +550,9 @@ def main():
         line["admm_tv"] = admm_tv_reconstruction(dev)
     if args.table1:
         line["table1"] = table1(dev)
+    if args.search or args.extra:
+        log("timing the axis and tilt sweeps")
+        line["search"] = search_sweeps(dev, data)
     if not args.no_cpu:
         log("timing the CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(data.double().cpu().numpy())

@@ -163,6 +163,21 @@ int lamino_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void
 int lamino_fbp_raw(const lamino_plan_t* plan, const void* d_raw, const float* d_dark,
                    const float* d_flat, double min_ratio, float* d_vol, void* stream);
 
+/* Slices of the FBP with a rotation-axis offset: the axis sits at detector
+ * column w/2 + center_shift (fractional allowed) instead of w/2, which in
+ * the Fourier route is the phase ramp exp(2 pi i m center_shift / w_p) on
+ * every row spectrum (a translation of the trigonometric interpolant of the
+ * padded rows); only slices z_first .. z_first + z_count - 1 of the x3
+ * transform are formed.  This is the single-slice reconstruction that the
+ * axis and tilt searches of the paper repeat over a sweep (Section "Mouse
+ * brain imaging"); a tilt sweep uses one plan per tilt (plans of one shape
+ * may share a workspace when their calls do not overlap).
+ * d_out: device float [z_count][n][n].  Errors: E_INVALID (slice range
+ * outside [0, nz), |center_shift| > (w_p - w)/2 or not finite), E_UNBOUND,
+ * E_HIP. */
+int lamino_fbp_slices(const lamino_plan_t* plan, const void* d_data, double center_shift,
+                      int z_first, int z_count, float* d_out, void* stream);
+
 /* Forward projection (eq:fwd via eq:fftfwd): d = L vol.
  * d_vol: device float vol[nz][n][n] (read only); d_data: device
  * d[n_theta][h][w] in data_dtype (written; E_INVALID for integer data).

@@ -27,6 +27,7 @@ EXPORTED = (
     "lamino_plan_bind",
     "lamino_fbp",
     "lamino_fbp_raw",
+    "lamino_fbp_slices",
     "lamino_fwd",
     "lamino_adj",
     "lamino_plan_profile",
@@ -134,6 +135,7 @@ def load_library(path=LIB_PATH):
     lib.lamino_last_error.restype = ctypes.c_char_p
     I, D = ctypes.c_int, ctypes.c_double
     lib.lamino_fbp_raw.argtypes = [P, P, P, P, D, P, P]
+    lib.lamino_fbp_slices.argtypes = [P, P, D, I, I, P, P]
     lib.lamino_direct_work_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.lamino_direct_fbp.argtypes = [P, P, P, P, P]
     lib.lamino_direct_adj.argtypes = [P, P, P, P]
@@ -147,7 +149,7 @@ def load_library(path=LIB_PATH):
                  "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
                  "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
                  "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink", "lamino_direct_work_bytes",
-                 "lamino_direct_fbp", "lamino_direct_adj", "lamino_fbp_raw",
+                 "lamino_direct_fbp", "lamino_direct_adj", "lamino_fbp_raw", "lamino_fbp_slices",
                  "lamino_admm_tv_state_bytes", "lamino_admm_tv"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -195,6 +197,11 @@ def lamino_fbp(plan, d_data, d_vol, stream):
 def lamino_fbp_raw(plan, d_raw, d_dark, d_flat, min_ratio, d_vol, stream):
     _check(load_library().lamino_fbp_raw(plan, d_raw, d_dark, d_flat, float(min_ratio), d_vol, stream),
            "lamino_fbp_raw")
+
+
+def lamino_fbp_slices(plan, d_data, center_shift, z_first, z_count, d_out, stream):
+    _check(load_library().lamino_fbp_slices(plan, d_data, float(center_shift), int(z_first),
+                                            int(z_count), d_out, stream), "lamino_fbp_slices")
 
 
 def lamino_fwd(plan, d_vol, d_data, stream):

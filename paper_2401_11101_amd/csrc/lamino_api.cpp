@@ -67,6 +67,8 @@ void layout_work(lamino_plan_s* p) {
   off += align256(p->bytes_G);
   p->off_g = off;
   off += align256(p->bytes_g);
+  p->off_phase = off;  // rotation-axis phase ramp, w_p complex values
+  off += align256((size_t)p->w_p * 8);
   p->work_bytes = off;
 }
 
@@ -491,9 +493,31 @@ int lamino_fbp_raw(const lamino_plan_t* p, const void* d_raw, const float* d_dar
   if (!d_dark || !d_flat) return fail(LAMINO_E_INVALID, "lamino_fbp_raw: NULL dark or flat field");
   if (!std::isfinite(min_ratio) || !(min_ratio > 0.0) || (float)min_ratio <= 0.f)
     return fail(LAMINO_E_INVALID, "lamino_fbp_raw: min_ratio must be a positive float");
-  hipError_t e = lam::run_backprojection(p, d_raw, d_vol, true, static_cast<hipStream_t>(stream),
-                                         d_dark, d_flat, (float)min_ratio);
+  lam::BackprojOpts o;
+  o.dark = d_dark;
+  o.flat = d_flat;
+  o.min_ratio = (float)min_ratio;
+  hipError_t e = lam::run_backprojection(p, d_raw, d_vol, true, static_cast<hipStream_t>(stream), o);
   return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp_raw");
+}
+
+int lamino_fbp_slices(const lamino_plan_t* p, const void* d_data, double center_shift, int z_first,
+                      int z_count, float* d_out, void* stream) {
+  const int c = check_call(p, d_data, d_out, "lamino_fbp_slices");
+  if (c) return c;
+  if (z_first < 0 || z_count < 1 || z_first > p->nz - z_count)
+    return fail(LAMINO_E_INVALID, "lamino_fbp_slices: slices [%d, %d + %d) outside [0, %d)", z_first,
+                z_first, z_count, p->nz);
+  const double room = 0.5 * (p->w_p - p->w);
+  if (!std::isfinite(center_shift) || std::fabs(center_shift) > room)
+    return fail(LAMINO_E_INVALID, "lamino_fbp_slices: |center_shift| must be <= (w_p - w) / 2 = %g",
+                room);
+  lam::BackprojOpts o;
+  o.center_shift = center_shift;
+  o.z_first = z_first;
+  o.z_count = z_count;
+  hipError_t e = lam::run_backprojection(p, d_data, d_out, true, static_cast<hipStream_t>(stream), o);
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp_slices");
 }
 
 int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {

@@ -63,7 +63,7 @@ struct lamino_plan_s {
   size_t table_bytes;
   int log2_twmax;
   // workspace layout (bytes)
-  size_t off_w1, off_D, off_G, off_g;
+  size_t off_w1, off_D, off_G, off_g, off_phase;
   size_t bytes_w1, bytes_D, bytes_G, bytes_g;
   size_t work_bytes;
   std::vector<unsigned char> host_tables;
@@ -101,9 +101,20 @@ struct StageTimer {
 };
 
 // The three operator pipelines (enqueue only).
+// Optional parts of a backprojection: the raw-count prologue (dark != NULL),
+// a rotation-axis offset (detector columns; applied as a phase ramp on the
+// row spectra) and the output slices [z_first, z_first + z_count) written
+// to d_vol[0 .. z_count).
+struct BackprojOpts {
+  const float* dark = nullptr;
+  const float* flat = nullptr;
+  float min_ratio = 0.f;
+  double center_shift = 0.0;
+  int z_first = 0;
+  int z_count = -1;  // -1: all nz slices
+};
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
-                              bool fbp_filter, hipStream_t s, const float* dark = nullptr,
-                              const float* flat = nullptr, float min_ratio = 0.f);
+                              bool fbp_filter, hipStream_t s, const BackprojOpts& o = BackprojOpts());
 hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        hipStream_t s);
 

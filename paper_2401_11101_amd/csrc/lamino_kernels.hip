@@ -84,7 +84,8 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 // function, stored as D[l][theta][k] (k = m mod w_p).
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
-                                                      int theta0, int rows) {
+                                                      const float2* __restrict__ phase, int theta0,
+                                                      int rows) {
   __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
@@ -106,9 +107,23 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e / wp, k = e - b * wp;
     const int l = l0 + b;
-    if (l < p.n_slab)
-      st_c(D, ((size_t)l * p.n_theta + th) * wp + k, cscale(res[e], filt[k]), p.storage_dtype);
+    if (l < p.n_slab) {
+      float2 v = cscale(res[e], filt[k]);
+      if (phase) v = cmul(v, phase[k]);
+      st_c(D, ((size_t)l * p.n_theta + th) * wp + k, v, p.storage_dtype);
+    }
   }
+}
+
+// Rotation-axis offset: exp(2 pi i m delta / w_p) for k = m mod w_p, in
+// double precision (a translation of the rows by delta columns).
+__global__ void k_axis_phase(float2* __restrict__ out, int wp, double delta) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= wp) return;
+  const int m = k < wp / 2 ? k : k - wp;
+  double sn, cs;
+  sincospi(2.0 * m * delta / wp, &sn, &cs);
+  out[k] = make_float2((float)cs, (float)sn);
 }
 
 // Inverse of the row step (forward projection): D[l][theta][.] -> inverse
@@ -757,7 +772,7 @@ __device__ __forceinline__ void x3_adj_loadb(const KParams& p, const void* g, in
 template <int PREC>
 __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void* __restrict__ g,
                                                           float* __restrict__ vol, int z0,
-                                                          int nzc) {
+                                                          int nzc, int out_z0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int ncol = p.n * p.n;
@@ -813,7 +828,7 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-      if (z < nzc) vol[(size_t)(z0 + z) * ncol + col] = acc[i][v] * p.x3_out_scale;
+      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * ncol + col] = acc[i][v] * p.x3_out_scale;
     }
 }
 
@@ -918,12 +933,17 @@ static inline char* wptr(const lamino_plan_s* p, size_t off) {
 }
 
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
-                              bool fbp_filter, hipStream_t s, const float* dark, const float* flat,
-                              float min_ratio) {
+                              bool fbp_filter, hipStream_t s, const BackprojOpts& o) {
   KParams kp = make_params(p, fbp_filter);
-  kp.dark = dark;
-  kp.flat = flat;
-  kp.min_ratio = min_ratio;
+  kp.dark = o.dark;
+  kp.flat = o.flat;
+  kp.min_ratio = o.min_ratio;
+  float2* phase = nullptr;
+  if (o.center_shift != 0.0) {
+    phase = reinterpret_cast<float2*>(wptr(p, p->off_phase));
+    hipLaunchKernelGGL(k_axis_phase, dim3(cdiv(p->w_p, 256)), dim3(256), 0, s, phase, p->w_p,
+                       o.center_shift);
+  }
   float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
   void* D = wptr(p, p->off_D);
   float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
@@ -936,7 +956,7 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp, d_data,
                        W1, t0, cp);
     hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
-                       (const float2*)W1, D, kp.filt, t0, rows_w);
+                       (const float2*)W1, D, kp.filt, (const float2*)phase, t0, rows_w);
   }
   const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
   const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
@@ -953,16 +973,17 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
                        (const float2*)G, g, s0, cols_g);
   }
   const int ncol = p->n * p->n;
-  for (int z0 = 0; z0 < p->nz; z0 += p->z_chunk) {
-    const int nzc = std::min(p->z_chunk, p->nz - z0);
+  const int zb = o.z_first, ze = o.z_count < 0 ? p->nz : o.z_first + o.z_count;
+  for (int z0 = zb; z0 < ze; z0 += p->z_chunk) {
+    const int nzc = std::min(p->z_chunk, ze - z0);
     StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
     const dim3 grid(cdiv(ncol, 32), cdiv(nzc, X3_ROWS));
     if (kp.storage_dtype == LAMINO_F32)
-      hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
+      hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
     else if (kp.storage_dtype == LAMINO_F16)
-      hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
+      hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
     else
-      hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc);
+      hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
   }
   return hipGetLastError();
 }

@@ -32,7 +32,8 @@ class Plan:
 
     def __init__(self, nz, n, n_theta, h, w, tilt, theta=None, data_dtype="f32",
                  storage_dtype="f32", filter="shepp-logan", pad_u=2.0, pad_v=2.0, kernel_m=0,
-                 z_chunk=0, slab_chunk=0, theta_chunk=0, hbm_budget=0, device=None, stream=None):
+                 z_chunk=0, slab_chunk=0, theta_chunk=0, hbm_budget=0, device=None, stream=None,
+                 work=None):
         self.shape_vol = (nz, n, n)
         self.shape_data = (n_theta, h, w)
         self.data_dtype = data_dtype
@@ -62,7 +63,12 @@ class Plan:
         tb, wb = _abi.lamino_plan_sizes(self._h)
         with torch.cuda.device(self.device):
             self.tables = torch.empty(max(tb, 256), dtype=torch.uint8, device=self.device)
-            self.work = torch.empty(max(wb, 256), dtype=torch.uint8, device=self.device)
+            if work is None:
+                work = torch.empty(max(wb, 256), dtype=torch.uint8, device=self.device)
+            elif work.dtype != torch.uint8 or work.numel() < wb or work.device != self.device:
+                raise ValueError(f"work must be a uint8 tensor of at least {wb} bytes on {self.device}")
+            # plans of one shape may share a workspace when their calls do not overlap
+            self.work = work
             _abi.lamino_plan_bind(self._h, ctypes.c_void_p(self.tables.data_ptr()),
                                   ctypes.c_void_p(self.work.data_ptr()), _stream_handle(stream))
 
@@ -105,6 +111,18 @@ class Plan:
         _abi.lamino_fbp_raw(self._h, ctypes.c_void_p(raw.data_ptr()), ctypes.c_void_p(dark.data_ptr()),
                             ctypes.c_void_p(flat.data_ptr()), min_ratio, ctypes.c_void_p(out.data_ptr()),
                             _stream_handle(stream))
+        return out
+
+    def fbp_slices(self, data, center_shift=0.0, z_first=0, z_count=None, out=None, stream=None):
+        """Slices z_first .. z_first + z_count - 1 of the FBP with the rotation
+        axis at detector column w/2 + center_shift."""
+        self._check(data, self.shape_data, self.torch_data_dtype, "data")
+        z_count = self.shape_vol[0] - z_first if z_count is None else z_count
+        shape = (z_count,) + self.shape_vol[1:]
+        out = torch.empty(shape, dtype=torch.float32, device=self.device) if out is None else out
+        self._check(out, shape, torch.float32, "out")
+        _abi.lamino_fbp_slices(self._h, ctypes.c_void_p(data.data_ptr()), center_shift, z_first, z_count,
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream))
         return out
 
     def adj(self, data, out=None, stream=None):
