@@ -74,7 +74,9 @@ def time_op(fn, steps, warmup, stream, plan=None):
 
 
 def algorithmic_work(info, storage_bytes, data_bytes):
-    """Algorithmic bytes / flops per FBP of each stage."""
+    """Algorithmic bytes / flops per FBP of each stage: reads and writes that
+    the stage must make once (input, output and the chunked intermediates it
+    owns), and 5 flops per Gaussian tap / 4 per x3 multiply-add."""
     n_slab, w_p, grid, M = info.n_slab, info.w_p, info.grid, info.kernel_m
     samples = n_slab * NT * (w_p - 1)
     return {
@@ -468,8 +470,9 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the operators would shard over angles, frequency slabs and volume columns "
+              "with two all-to-all exchanges; only the one-GPU share is built)", file=sys.stderr)
         sys.exit(2)
     from paper_2401_11101_amd import Plan
 
