@@ -42,13 +42,17 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
   const int npairs = min(pairs_per_block, (rows + 1) / 2 - pair0);
   lds_zero(buf, npairs * wp);
   __syncthreads();
-  for (int e = threadIdx.x; e < npairs * w; e += NTF) {
-    const int j = e / w, c = e - j * w;
-    const int ra = 2 * (pair0 + j), rb = ra + 1;
-    const float a = ld_r(data, (size_t)ra * w + c, p.data_dtype);
-    const float b = rb < rows ? ld_r(data, (size_t)rb * w + c, p.data_dtype) : 0.f;
-    buf[j * wp + ((c - w / 2) & (wp - 1))] = make_float2(a, b);
-  }
+  // the block's rows are contiguous in memory: row 2 j is the real part of
+  // transform j, row 2 j + 1 its imaginary part
+  const int row0 = 2 * pair0;
+  const int nrows = min(2 * npairs, rows - row0);
+  float* bf = reinterpret_cast<float*>(buf);
+  stage_in<float>(
+      nrows * w, [&](int e) { return ld_r(data, (size_t)row0 * w + e, p.data_dtype); },
+      [&](int e, float v) {
+        const int rr = e / w, c = e - rr * w;
+        bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
+      });
   __syncthreads();
   block_fft(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
   for (int e = threadIdx.x; e < npairs * wp; e += NTF) {
@@ -58,12 +62,9 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
   }
   __syncthreads();
   block_fft(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
-  for (int e = threadIdx.x; e < npairs * w; e += NTF) {
-    const int j = e / w, c = e - j * w;
-    const int ra = 2 * (pair0 + j), rb = ra + 1;
-    const float2 v = buf[j * wp + ((c - w / 2) & (wp - 1))];
-    out[(size_t)ra * w + c] = v.x;
-    if (rb < rows) out[(size_t)rb * w + c] = v.y;
+  for (int e = threadIdx.x; e < nrows * w; e += NTF) {
+    const int rr = e / w, c = e - rr * w;
+    out[(size_t)row0 * w + e] = bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)];
   }
 }
 
