@@ -171,3 +171,33 @@ def test_tv_calls_validate_arguments_on_the_host(lib):
         _abi.lamino_admm_tv(plan, P(256), P(512), 0.1, 1.0, 1, 1, 0, P(768), None)
     assert e.value.code == _abi.LAMINO_E_UNBOUND
     _abi.lamino_plan_destroy(plan)
+
+
+def test_new_entry_points_validate_on_the_host(lib):
+    P = ctypes.c_void_p
+    plan = _abi.lamino_plan(_geom(), _abi.lamino_opts_default())
+    # every call on an unbound plan fails before touching the device
+    for call in (lambda: _abi.lamino_fbp_raw(plan, P(256), P(512), P(768), 1e-6, P(1024), None),
+                 lambda: _abi.lamino_fbp_slices(plan, P(256), 0.0, 0, 1, P(512), None),
+                 lambda: _abi.lamino_direct_adj(plan, P(256), P(512), None),
+                 lambda: _abi.lamino_direct_fbp(plan, P(256), P(512), P(768), None)):
+        with pytest.raises(_abi.LaminoError) as e:
+            call()
+        assert e.value.code == _abi.LAMINO_E_UNBOUND
+    # the direct workspace holds the filtered rows, n_theta h w float32
+    assert _abi.lamino_direct_work_bytes(plan) == _a256(12 * 14 * 18 * 4)
+    _abi.lamino_plan_destroy(plan)
+
+
+def test_integer_data_types_are_accepted_for_input(lib):
+    for dt in (_abi.LAMINO_U8, _abi.LAMINO_U16):
+        o = _abi.lamino_opts_default()
+        o.data_dtype = dt
+        plan = _abi.lamino_plan(_geom(), o)
+        _abi.lamino_plan_destroy(plan)
+    o = _abi.lamino_opts_default()
+    o.data_dtype = 5
+    assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID
+    o = _abi.lamino_opts_default()
+    o.storage_dtype = _abi.LAMINO_U8  # integer types are not storage types
+    assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID
