@@ -185,6 +185,36 @@ def cpu_baseline(data_np, budget_s=15.0, max_slabs=64):
                       f"({t_det + t_slabs:.1f} s measured, {t_total:.0f} s extrapolated)"}
 
 
+def cpu_direct_fbp(data_np, budget_s=5.0):
+    """Oracle O1 (the direct line-integral FBP in C, FP64, OpenMP over all the
+    host's threads) on a bounded sample: the row filter of all projections
+    (numpy), then z slices spread over the volume for `budget_s` seconds,
+    scaled to all nz slices."""
+    from oracle import direct, filters
+    from oracle.geometry import Geometry
+
+    g = Geometry(nz=NZ, n=N, n_theta=NT, h=H, w=W, phi=TILT)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    fd = direct.filter_rows(data_np, g, filters.SHEPP_LOGAN)
+    t_filter = time.perf_counter() - t0
+    t_slices, done = 0.0, 0
+    for k in range(NZ):
+        z = (k * 97) % NZ
+        t1 = time.perf_counter()
+        direct.adjoint(fd, g, z_range=(z, z + 1))
+        t_slices += time.perf_counter() - t1
+        done += 1
+        if t_slices >= budget_s:
+            break
+    t_total = t_filter + t_slices / done * NZ
+    return {"value": round(NZ * N * N / t_total / 1e9, 9), "unit": "GVoxel/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"O1 direct bilinear FBP (C, FP64, OpenMP): row filter of all {NT} projections "
+                      f"and {done} of {NZ} z slices, scaled linearly ({t_filter + t_slices:.1f} s "
+                      f"measured, {t_total:.0f} s extrapolated)"}
+
+
 def serving(dev, count, rate=20.0):
     """Poisson stream of fp16-gridded FBP requests over three size classes."""
     from paper_2401_11101_amd.serve import Server, run_poisson
@@ -559,6 +589,8 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle baseline (bounded sample)")
         line["cpu_baseline"] = cpu_baseline(data.double().cpu().numpy())
+        log("timing the CPU direct-FBP oracle (bounded sample)")
+        line["cpu_direct_fbp"] = cpu_direct_fbp(data.double().cpu().numpy())
     print(json.dumps(line), flush=True)
 
 
