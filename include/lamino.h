@@ -111,11 +111,18 @@ typedef struct {
   size_t table_bytes, work_bytes;
   size_t off_spectra, bytes_spectra; /* D[l][theta][k] in the workspace       */
   size_t off_slabs, bytes_slabs;     /* g[l][y][x] in the workspace           */
-  double spectra_scale; /* power of two by which the stored D and g of the
-                           adjoint / FBP direction exceed their definition:
-                           h_p w_p / 64 for F16 storage (keeps typical values
-                           out of the float16 subnormal range), else 1; the
-                           x3 transform removes it from the output            */
+  double spectra_scale; /* power of two by which the stored D and g of an
+                           FBP exceed their definition: h_p w_p / 64 for F16
+                           storage (keeps typical values out of the float16
+                           subnormal range), else 1; the x3 transform removes
+                           it.  With F16 storage L* uses spectra_scale /
+                           2^ceil(log2 n_theta), the forward L carries
+                           1 / 2^ceil(log2 nz) on g and 2^15 / 2^ceil(log2
+                           32 n^2) on D, and every call also scales its input
+                           by 2^-e so that its largest magnitude lies in
+                           [0.5, 1) (a scan of the input, undone at the
+                           output): float16 intermediates stay in range for
+                           any input scale                                    */
 } lamino_info;
 
 /* Fill *opts with defaults (F32 data and storage, Shepp-Logan, pad 2). */

@@ -51,6 +51,7 @@ double window(double k, int kind) {
 }
 
 constexpr size_t kChunkTarget = 512u << 20;  // bytes per chunked intermediate
+constexpr int kAbsmaxBlocks = 1024;          // partial maxima of the float16 input scan
 
 void layout_work(lamino_plan_s* p) {
   const size_t sb = lam::storage_bytes(p->opts.storage_dtype);
@@ -69,6 +70,8 @@ void layout_work(lamino_plan_s* p) {
   off += align256(p->bytes_g);
   p->off_phase = off;  // rotation-axis phase ramp, w_p complex values
   off += align256((size_t)p->w_p * 8);
+  p->off_dyn = off;    // float16 per-call input factor and block partial maxima
+  off += align256((size_t)(2 + kAbsmaxBlocks) * 4);
   p->work_bytes = off;
 }
 
@@ -140,14 +143,19 @@ void build_tables(lamino_plan_s* p) {
   // s = h_p w_p / 64 (exact), which keeps their typical magnitudes away from
   // the float16 subnormal range; the x3 transform multiplies its output by 1/s.
   p->spectra_scale = p->opts.storage_dtype == LAMINO_F16 ? (double)p->h_p * p->w_p / 64.0 : 1.0;
+  // L* lacks the filter's pi / n_theta: its spectra and slab planes are
+  // ~n_theta times larger, so its factor is smaller by the next power of two
+  p->adj_scale = p->opts.storage_dtype == LAMINO_F16 ? p->spectra_scale / pow2_at_least(p->n_theta)
+                                                      : 1.0;
   const double norm = p->spectra_scale / ((double)p->h_p * p->w_p);
+  const double norm_adj = p->adj_scale / ((double)p->h_p * p->w_p);
   for (int k = 0; k < p->w_p; ++k) {
     const int m = k < p->w_p / 2 ? k : k - p->w_p;
     const double km = (double)m / p->w_p;
     const bool nyq = (k == p->w_p / 2);
     ffbp[k] = nyq ? 0.f
                   : (float)(M_PI / p->n_theta * cphi * std::fabs(km) * window(km, p->opts.filter) * norm);
-    fadj[k] = nyq ? 0.f : (float)norm;
+    fadj[k] = nyq ? 0.f : (float)norm_adj;
   }
   // psi correction of the Gaussian USFFT per axis
   float* deap = reinterpret_cast<float*>(base + p->off_deapod);
@@ -239,7 +247,20 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.deapod = reinterpret_cast<const float*>(t + p->off_deapod);
   k.x3a = reinterpret_cast<const unsigned short*>(t + p->off_x3a);
   k.x3f = reinterpret_cast<const unsigned short*>(t + p->off_x3f);
-  k.x3_out_scale = (float)(1.0 / p->spectra_scale);
+  k.x3_out_scale = (float)(1.0 / (fbp_filter ? p->spectra_scale : p->adj_scale));
+  if (p->opts.storage_dtype == LAMINO_F16) {
+    // forward direction, input scaled into [0.5, 1): the slab planes sum nz
+    // voxels (factor 1 / 2^ceil(log2 nz)); the spectra sum the (1.45 n)^2
+    // psi-corrected plane values times at most ~13 Gaussian tap weights,
+    // kept below 2^15 by 2^15 / 2^ceil(log2(32 n^2))
+    k.fwd_g_scale = (float)(1.0 / pow2_at_least(p->nz));
+    k.fwd_D_scale = (float)(32768.0 / pow2_at_least(32.0 * p->n * p->n));
+    k.dyn = reinterpret_cast<const float*>(static_cast<const char*>(p->d_work) + p->off_dyn);
+  } else {
+    k.fwd_g_scale = 1.f;
+    k.fwd_D_scale = 1.f;
+    k.dyn = nullptr;
+  }
   k.x3a_rows = p->x3a_rows;
   k.x3a_k = p->x3a_k;
   k.x3f_rows = p->x3f_rows;

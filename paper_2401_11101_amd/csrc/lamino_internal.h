@@ -32,6 +32,13 @@ struct KParams {
   const unsigned short* x3f;  // [2][x3f_rows][x3f_k]
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
   float x3_out_scale;     // 1 / (power-of-two factor carried by the stored spectra)
+  // float16 range control of the forward direction (1 for other storage):
+  // exact powers of two carried by the stored slab planes g and spectra D
+  float fwd_g_scale, fwd_D_scale;
+  // float16 storage: device [f, 1/f], f = 2^-e with the call's input scaled
+  // into [0.5, 1) by f (first kernel) and the output by 1/f (last kernel);
+  // NULL for other storage types
+  const float* dyn;
   const float2* tw;       // [2^log2_twmax] exp(-2 pi i t / 2^log2_twmax)
   // direct (line-integral) path
   const double2* trig_d;  // [n_theta] (cos, sin) in double precision
@@ -58,12 +65,13 @@ struct lamino_plan_s {
   // table layout (bytes)
   size_t off_trig, off_filt_fbp, off_filt_adj, off_deapod, off_x3a, off_x3f, off_tw;
   size_t off_trig_d, off_filt_dir;
-  double spectra_scale;  // power of two folded into the filter tables
+  double spectra_scale;  // power of two folded into the FBP filter table
+  double adj_scale;      // the same for the L* filter table
   int x3a_rows, x3a_k, x3f_rows, x3f_k;
   size_t table_bytes;
   int log2_twmax;
   // workspace layout (bytes)
-  size_t off_w1, off_D, off_G, off_g, off_phase;
+  size_t off_w1, off_D, off_G, off_g, off_phase, off_dyn;
   size_t bytes_w1, bytes_D, bytes_G, bytes_g;
   size_t work_bytes;
   std::vector<unsigned char> host_tables;

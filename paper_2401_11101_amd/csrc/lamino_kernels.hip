@@ -19,6 +19,7 @@
 // float32 throughout; the matrix-core products take 16-bit operands (bf16
 // hi + lo splits for float32 data); stored spectra and slab planes may be
 // float16 / bfloat16.
+#include <cmath>
 #include <type_traits>
 
 #include "lamino_common.h"
@@ -49,15 +50,18 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   const int wide = 2 * cp;
   float* bf = reinterpret_cast<float*>(buf);
   const size_t row0 = (size_t)th * p.h;
+  const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
   stage_in<float>(
       p.h * wide,
       [&](int e) {
         const int r = e / wide, c = c0 + e - r * wide;
         if (c >= p.w) return 0.f;
-        const float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
-        if (!p.dark) return v;
-        const size_t q = (size_t)r * p.w + c;
-        return flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
+        float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
+        if (p.dark) {
+          const size_t q = (size_t)r * p.w + c;
+          v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
+        }
+        return v * fin;
       },
       [&](int e, float v) {
         const int r = e / wide, cl = e - r * wide;
@@ -199,12 +203,13 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   const float2* res = buf;
   const int wide = 2 * cp;
   const float* bf = reinterpret_cast<const float*>(res);
+  const float out = scale * (p.dyn ? p.dyn[1] : 1.f);
   for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
     const int r = e / wide, cl = e - r * wide;
     const int c = c0 + cl;
     if (c >= p.w) continue;
     const int pos = (r - p.h / 2) & (hp - 1);
-    st_r(data, ((size_t)th * p.h + r) * p.w + c, bf[2 * ((cl >> 1) * hp + pos) + (cl & 1)] * scale,
+    st_r(data, ((size_t)th * p.h + r) * p.w + c, bf[2 * ((cl >> 1) * hp + pos) + (cl & 1)] * out,
          p.data_dtype);
   }
 }
@@ -589,7 +594,8 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
             acc.x = fmaf(wy[jy], row.x, acc.x);
             acc.y = fmaf(wy[jy], row.y, acc.y);
           }
-          st_c(D, ((size_t)l * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)), acc, p.storage_dtype);
+          st_c(D, ((size_t)l * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)),
+               cscale(acc, p.fwd_D_scale), p.storage_dtype);
         }
       }
     }
@@ -779,6 +785,7 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
   const int col = blockIdx.x * 32 + r;
   const int zt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;
   if (zt >= nzc) return;
+  const float outs = p.x3_out_scale * (p.dyn ? p.dyn[1] : 1.f);
   const int K = p.x3a_k;
   int arow[X3_ZT];
 #pragma unroll
@@ -828,7 +835,7 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * ncol + col] = acc[i][v] * p.x3_out_scale;
+      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * ncol + col] = acc[i][v] * outs;
     }
 }
 
@@ -867,6 +874,8 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float
     }
   }
   if (!cok) return;
+  // float16 storage: the call's input factor and the planes' static factor
+  const float gs = p.fwd_g_scale * (p.dyn ? p.dyn[0] : 1.f);
   // rows 2l (re) and 2l + 1 (im) sit in accumulators v and v + 1 (v % 4 = 0, 2)
 #pragma unroll
   for (int i = 0; i < X3_ZT; ++i)
@@ -875,12 +884,64 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float
       const int m = mt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
       const int l = m >> 1;
       if (l < p.n_slab)
-        st_c(g, (size_t)l * ncol + col, make_float2(acc[i][v], acc[i][v + 1]), p.storage_dtype);
+        st_c(g, (size_t)l * ncol + col, make_float2(acc[i][v] * gs, acc[i][v + 1] * gs),
+             p.storage_dtype);
     }
+}
+
+// Float16 storage: the call's input is scaled by f = 2^-e so that its largest
+// magnitude lies in [0.5, 1), which keeps the stored spectra and slab planes
+// inside the float16 range for any input scale.  Block maxima first, then
+// one block forms f and 1/f (exact powers of two) in dyn[0], dyn[1].
+constexpr int ABSMAX_BLOCKS = 1024;
+
+__global__ __launch_bounds__(256) void k_absmax_partial(const void* __restrict__ x, size_t n, int dt,
+                                                         float* __restrict__ part) {
+  __shared__ float red[4];
+  float m = 0.f;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m = fmaxf(m, fabsf(ld_r(x, i, dt)));
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// nb partial maxima (0: none) and a host-known bound `extra`
+__global__ __launch_bounds__(256) void k_absmax_final(float* __restrict__ dyn, int nb, float extra) {
+  __shared__ float red[4];
+  float m = threadIdx.x == 0 ? extra : 0.f;
+  for (int i = threadIdx.x; i < nb; i += 256) m = fmaxf(m, dyn[2 + i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int e = 0;
+    if (m > 0.f && isfinite(m)) frexpf(m, &e);  // m = frac 2^e, frac in [0.5, 1)
+    dyn[0] = ldexpf(1.f, -e);
+    dyn[1] = ldexpf(1.f, e);
+  }
 }
 
 // ================================================================ drivers
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// Sets the float16 input factor of a call from its input (x != NULL) or from
+// a known bound alone.
+static void input_factor(const KParams& kp, const void* x, size_t n, int dt, float bound,
+                         hipStream_t s) {
+  float* dyn = const_cast<float*>(kp.dyn);
+  int nb = 0;
+  if (x) {
+    nb = (int)std::min<size_t>(ABSMAX_BLOCKS, std::max<size_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, s, x, n, dt, dyn + 2);
+  }
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, dyn, nb, bound);
+}
 
 static int spread_tile(const KParams& p) { return p.grid <= 128 ? (p.grid < 32 ? p.grid : 32) : 64; }
 
@@ -938,6 +999,11 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   kp.dark = o.dark;
   kp.flat = o.flat;
   kp.min_ratio = o.min_ratio;
+  if (kp.dyn) {
+    // raw counts: the corrected values are bounded by -log(min_ratio)
+    if (o.dark) input_factor(kp, nullptr, 0, 0, -std::log(o.min_ratio), s);
+    else input_factor(kp, d_data, (size_t)p->n_theta * p->h * p->w, p->opts.data_dtype, 0.f, s);
+  }
   float2* phase = nullptr;
   if (o.center_shift != 0.0) {
     phase = reinterpret_cast<float2*>(wptr(p, p->off_phase));
@@ -995,6 +1061,7 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
   void* g = wptr(p, p->off_g);
   const int ncol = p->n * p->n;
+  if (kp.dyn) input_factor(kp, d_vol, (size_t)p->nz * ncol, LAMINO_F32, 0.f, s);
   {
     StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
     hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, 32), cdiv(2 * p->n_slab, X3_ROWS)),
@@ -1016,7 +1083,8 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   }
   const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
   const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
-  const float scale = (float)(1.0 / ((double)p->h_p * p->w_p));
+  // 1 / (h_p w_p) of the inverse DFT, and the static float16 factors removed
+  const float scale = (float)(1.0 / ((double)p->h_p * p->w_p) / ((double)kp.fwd_g_scale * kp.fwd_D_scale));
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);

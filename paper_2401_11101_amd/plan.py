@@ -174,8 +174,9 @@ class Plan:
         return _abi.lamino_plan_stage_times(self._h, reset)
 
     def spectra(self):
-        """Stored spectra D[l][theta][k] after an adjoint or FBP call (complex),
-        with the storage scale (info.spectra_scale) divided out."""
+        """Stored spectra D[l][theta][k] after an FBP call (complex), with the
+        storage scale (info.spectra_scale) divided out.  With float16 storage
+        they also carry the call's power-of-two input factor."""
         i = self.info
         raw = self.work[i.off_spectra:i.off_spectra + i.bytes_spectra]
         n_theta, h, w = self.shape_data

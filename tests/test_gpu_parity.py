@@ -230,3 +230,29 @@ def test_stage_profiling_counts_launches_and_time():
     assert st["x3"][1] == 4
     assert all(ms > 0 for ms, _ in st.values())
     assert all(n == 0 for _, n in plan.stage_times().values())
+
+
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 1e3])
+def test_float16_storage_keeps_range_at_full_size(scale):
+    # 256^3 / 400 projections: float16-stored spectra and slab planes stay in
+    # range for any input scale (a per-call power-of-two factor), in both
+    # directions; compared with the float32 path, which the sampled-column
+    # test pins to the exact sums.
+    nz = n = h = w = 256
+    nt = 400
+    tilt = np.deg2rad(25.0)
+    print(f"float16 range, input scale {scale:g}", flush=True)
+    ells = synth.random_ellipsoids(50, nz, n, seed=0)
+    vol = synth.voxelize_ellipsoids(ells, nz, n, device=dev(), dtype=torch.float32) * scale
+    d = synth.project_ellipsoids(ells, nt, h, w, tilt, device=dev(), dtype=torch.float32) * scale
+    p32 = Plan(nz, n, nt, h, w, tilt)
+    a_fwd, a_adj, a_fbp = p32.fwd(vol), p32.adj(d), p32.fbp(d)
+    del p32
+    p16 = Plan(nz, n, nt, h, w, tilt, storage_dtype="f16")
+    b_fwd, b_adj, b_fbp = p16.fwd(vol), p16.adj(d), p16.fbp(d)
+    torch.cuda.synchronize()
+    errs = [float((b - a).norm() / a.norm()) for a, b in ((a_fwd, b_fwd), (a_adj, b_adj), (a_fbp, b_fbp))]
+    print(f"  f16 vs f32: fwd {errs[0]:.2e} adj {errs[1]:.2e} fbp {errs[2]:.2e}")
+    for b in (b_fwd, b_adj, b_fbp):
+        assert bool(torch.isfinite(b).all())
+    assert max(errs) < TOL_LOWP

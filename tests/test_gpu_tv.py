@@ -298,3 +298,19 @@ def test_full_size_subproblem_decreases_and_dual_is_feasible():
         assert float(dev_) < 1e-3 * alpha
     print("  F:", ", ".join(f"{f:.6e}" for f in F))
     assert F[0] > F[1] > F[2]
+
+
+@pytest.mark.parametrize("storage, bar", [("f16", 1e-2), ("bf16", 5e-2)])
+def test_admm_with_16bit_storage_matches_oracle(storage, bar):
+    # The 16-bit operators differ from the exact ones by 2.9e-4 (f16) and
+    # 1.2e-3 (bf16) on this instance; the float32 run shows the 3 x 3
+    # iterations amplifying operator error about tenfold (3e-6 -> 3e-5), so
+    # mu is held to ~3x that estimate.  psi and lambda, which threshold
+    # gradient differences, are reported.
+    print(f"admm {storage} storage", flush=True)
+    mu, psi, lam = _gpu(0.1, 1.0, 3, 3, storage=storage)
+    mu_o, psi_o, lam_o = _oracle(0.1, 1.0, 3, 3, None)
+    e = (rel(mu, mu_o), rel(psi, psi_o), rel(lam, lam_o))
+    print(f"  rel-L2 mu {e[0]:.2e} psi {e[1]:.2e} lambda {e[2]:.2e}")
+    assert np.all(np.isfinite(mu)) and np.all(np.isfinite(lam))
+    assert e[0] < bar
