@@ -107,3 +107,13 @@ def test_full_size_prologue_equals_corrected_fbp():
     e = float((a - b).abs().max() / b.abs().max())
     print(f"  max rel {e:.2e}")
     assert e < 2e-6
+
+
+def test_fbp_raw_with_float16_storage_matches_oracle():
+    g, raw, dark, flat = _raw()
+    plan = Plan(NZ, N, NT, H, W, PHI, data_dtype="u16", storage_dtype="f16")
+    out = to_np(plan.fbp_raw(_dev_int(raw), to_dev(dark), to_dev(flat)))
+    dc = prologue.flat_dark_log(raw, dark.astype(np.float64), flat.astype(np.float64), 1e-6)
+    e = rel(out, nudft.fbp(dc, g))
+    print(f"  fp16 storage rel-L2 {e:.2e}")
+    assert e < 1e-2

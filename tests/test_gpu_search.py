@@ -102,3 +102,17 @@ def test_slice_arguments_are_checked():
     room = (plan.info.w_p - W) / 2
     with pytest.raises(_abi.LaminoError):
         plan.fbp_slices(to_dev(d), room + 0.5)
+
+
+def test_slices_with_chunked_plan_and_offset():
+    # z chunks of 3, slab chunks of 2, theta chunks of 7: the slice range
+    # starts inside a z chunk; the offset applies in every theta chunk
+    g, d = _data(4)
+    full = Plan(NZ, N, NT, H, W, PHI)
+    chunked = Plan(NZ, N, NT, H, W, PHI, z_chunk=3, slab_chunk=2, theta_chunk=7)
+    a = chunked.fbp_slices(to_dev(d), 1.75, z_first=4, z_count=9)
+    b = full.fbp_slices(to_dev(d), 1.75)[4:13]
+    torch.cuda.synchronize()
+    e = float((a - b).abs().max() / b.abs().max())
+    print(f"  chunked slices vs unchunked: max rel {e:.1e}")
+    assert e < 1e-6
