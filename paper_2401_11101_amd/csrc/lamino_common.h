@@ -25,6 +25,19 @@ LAM_HD float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); 
 LAM_HD float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
 LAM_HD float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
 
+// e / d for 0 <= e < 2^24 and 1 <= d < 2^24, given inv = 1.0f / d: the
+// float product is within one of the quotient, and one correction step
+// makes it exact.  A handful of instructions instead of the generic 32-bit
+// integer division (checked exhaustively over small ranges by the host
+// self-test).
+LAM_HD int div24(int e, int d, float inv) {
+  int q = (int)((float)e * inv);
+  const int r = e - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
+}
+
 LAM_HD int ilog2(int n) {
   int l = 0;
   while ((1 << l) < n) ++l;

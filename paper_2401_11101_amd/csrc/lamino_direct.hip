@@ -47,10 +47,11 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
   const int row0 = 2 * pair0;
   const int nrows = min(2 * npairs, rows - row0);
   float* bf = reinterpret_cast<float*>(buf);
+  const float iw = 1.f / (float)w;
   stage_in<float>(
       nrows * w, [&](int e) { return ld_r(data, (size_t)row0 * w + e, p.data_dtype); },
       [&](int e, float v) {
-        const int rr = e / w, c = e - rr * w;
+        const int rr = div24(e, w, iw), c = e - rr * w;
         bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
       });
   __syncthreads();
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
   __syncthreads();
   block_fft(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
   for (int e = threadIdx.x; e < nrows * w; e += NTF) {
-    const int rr = e / w, c = e - rr * w;
+    const int rr = div24(e, w, iw), c = e - rr * w;
     out[(size_t)row0 * w + e] = bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)];
   }
 }

@@ -48,13 +48,14 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   lds_zero(buf, cp * hp);
   __syncthreads();
   const int wide = 2 * cp;
+  const float iwide = 1.f / (float)wide;
   float* bf = reinterpret_cast<float*>(buf);
   const size_t row0 = (size_t)th * p.h;
   const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
   stage_in<float>(
       p.h * wide,
       [&](int e) {
-        const int r = e / wide, c = c0 + e - r * wide;
+        const int r = div24(e, wide, iwide), c = c0 + e - r * wide;
         if (c >= p.w) return 0.f;
         float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
         if (p.dark) {
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
         return v * fin;
       },
       [&](int e, float v) {
-        const int r = e / wide, cl = e - r * wide;
+        const int r = div24(e, wide, iwide), cl = e - r * wide;
         bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
       });
   __syncthreads();
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   for (int e = threadIdx.x; e < p.n_slab * wide; e += NTF) {
-    const int l = e / wide, cl = e - l * wide;
+    const int l = div24(e, wide, iwide), cl = e - l * wide;
     const int c = c0 + cl;
     if (c >= p.w) continue;
     const float2* z = res + (cl >> 1) * hp;
@@ -99,17 +100,18 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
   const int nr = min(rows, p.n_slab - l0);
+  const float iw = 1.f / (float)p.w;
   stage_in<float2>(
       nr * p.w, [&](int e) { return w1[base + (size_t)l0 * p.w + e]; },
       [&](int e, float2 v) {
-        const int b = e / p.w, c = e - b * p.w;
+        const int b = div24(e, p.w, iw), c = e - b * p.w;
         buf[b * wp + ((c - p.w / 2) & (wp - 1))] = v;
       });
   __syncthreads();
   block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * wp; e += NTF) {
-    const int b = e / wp, k = e - b * wp;
+    const int b = e >> p.log2_wp, k = e & (wp - 1);
     const int l = l0 + b;
     if (l < p.n_slab) {
       float2 v = cscale(res[e], filt[k]);
@@ -155,8 +157,9 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
   block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
+  const float iw = 1.f / (float)p.w;
   for (int e = threadIdx.x; e < rows * p.w; e += NTF) {
-    const int b = e / p.w, c = e - b * p.w;
+    const int b = div24(e, p.w, iw), c = e - b * p.w;
     const int l = l0 + b;
     if (l < p.n_slab) w1[base + (size_t)l * p.w + c] = res[b * wp + ((c - p.w / 2) & (wp - 1))];
   }
@@ -178,17 +181,18 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   lds_zero(buf, cp * hp);
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
+  const float icp = 1.f / (float)cp;
   stage_in<float4>(
       p.n_slab * cp,
       [&](int e) {
-        const int l = e / cp, pp = e - l * cp;
+        const int l = div24(e, cp, icp), pp = e - l * cp;
         const int ca = c0 + 2 * pp, cb = ca + 1;
         const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
         const float2 xb = cb < p.w ? w1[base + (size_t)l * p.w + cb] : make_float2(0.f, 0.f);
         return make_float4(xa.x, xa.y, xb.x, xb.y);
       },
       [&](int e, float4 x) {
-        const int l = e / cp, pp = e - l * cp;
+        const int l = div24(e, cp, icp), pp = e - l * cp;
         float2* z = buf + pp * hp;
         // x = (Re X_a, Im X_a, Re X_b, Im X_b)
         if (l == 0) {
@@ -202,10 +206,11 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   block_fft(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int wide = 2 * cp;
+  const float iwide = 1.f / (float)wide;
   const float* bf = reinterpret_cast<const float*>(res);
   const float out = scale * (p.dyn ? p.dyn[1] : 1.f);
   for (int e = threadIdx.x; e < p.h * wide; e += NTF) {
-    const int r = e / wide, cl = e - r * wide;
+    const int r = div24(e, wide, iwide), cl = e - r * wide;
     const int c = c0 + cl;
     if (c >= p.w) continue;
     const int pos = (r - p.h / 2) & (hp - 1);
@@ -516,8 +521,9 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
   const float e2b = __expf(-2.f * p.beta);
   const int half_m = (p.w_p >> 1) - 1;
   const size_t gbase = (size_t)blockIdx.x * p.grid * p.grid;
+  const float iP = 1.f / (float)P;
   for (int e = threadIdx.x; e < P * P; e += NT) {
-    const int yy = e / P, xx = e - yy * P;
+    const int yy = div24(e, P, iP), xx = e - yy * P;
     const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
     st[e] = G[gbase + (size_t)ky * p.grid + kx];
   }
@@ -620,8 +626,9 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
   __syncthreads();
   block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
+  const float in = 1.f / (float)p.n;
   for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
-    const int b = e / p.n, ix = e - b * p.n;
+    const int b = div24(e, p.n, in), ix = e - b * p.n;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
   }
 }
@@ -631,15 +638,16 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
+  const float icols = 1.f / (float)cols;
   const float2* gg = G + (size_t)blockIdx.y * N * N;
   stage_in<float2>(
       cols * N,
       [&](int e) {
-        const int k2 = e / cols, c = e - k2 * cols;
+        const int k2 = div24(e, cols, icols), c = e - k2 * cols;
         return (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) {
-        const int k2 = e / cols, c = e - k2 * cols;
+        const int k2 = div24(e, cols, icols), c = e - k2 * cols;
         buf[c * N + k2] = v;
       });
   __syncthreads();
@@ -647,7 +655,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   const float2* res = buf;
   const int l = slab0 + blockIdx.y;
   for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
-    const int y = e / cols, c = e - y * cols;
+    const int y = div24(e, cols, icols), c = e - y * cols;
     const int ix = ix0 + c;
     if (ix >= p.n) continue;
     const float2 v = cscale(res[c * N + ((y - p.n / 2) & (N - 1))], p.deapod[ix] * p.deapod[y]);
@@ -660,18 +668,19 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
   __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
+  const float icols = 1.f / (float)cols;
   const int l = slab0 + blockIdx.y;
   lds_zero(buf, cols * N);
   __syncthreads();
   stage_in<float2>(
       cols * p.n,
       [&](int e) {
-        const int y = e / cols, ix = ix0 + e - y * cols;
+        const int y = div24(e, cols, icols), ix = ix0 + e - y * cols;
         return ix < p.n ? ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype)
                         : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) {
-        const int y = e / cols, c = e - y * cols;
+        const int y = div24(e, cols, icols), c = e - y * cols;
         const int ix = ix0 + c;
         if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
       });
@@ -680,7 +689,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
   const float2* res = buf;
   float2* gg = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < cols * N; e += NTF) {
-    const int k2 = e / cols, c = e - k2 * cols;
+    const int k2 = div24(e, cols, icols), c = e - k2 * cols;
     if (ix0 + c < p.n) gg[(size_t)k2 * N + ix0 + c] = res[c * N + k2];
   }
 }
@@ -691,24 +700,25 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
+  const float in = 1.f / (float)p.n;
   lds_zero(buf, rows * N);
   __syncthreads();
   stage_in<float2>(
       min(rows, N - r0) * p.n,
       [&](int e) {
-        const int b = e / p.n, ix = e - b * p.n;
+        const int b = div24(e, p.n, in), ix = e - b * p.n;
         return g[(size_t)(r0 + b) * N + ix];
       },
       [&](int e, float2 v) {
-        const int b = e / p.n, ix = e - b * p.n;
+        const int b = div24(e, p.n, in), ix = e - b * p.n;
         buf[b * N + ((ix - p.n / 2) & (N - 1))] = v;
       });
   __syncthreads();
   block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * N; e += NTF) {
-    const int b = e / N;
-    if (r0 + b < N) g[(size_t)(r0 + b) * N + (e - b * N)] = res[e];
+    const int b = e >> p.log2_grid;
+    if (r0 + b < N) g[(size_t)(r0 + b) * N + (e & (N - 1))] = res[e];
   }
 }
 

@@ -9,6 +9,7 @@
 //          its wrapped base cell, inside that tile's candidate interval
 //          (interpolation).
 //  ring    the centre-out tile order is a bijection onto the ntx x ntx tiles.
+//  div24   the float-reciprocal integer division equals e / d.
 //  xcd     the XCD-grouped tile order of the volume stencil kernels (64 x 4
 //          x 16 voxel tiles) covers every voxel of ragged volumes exactly
 //          once, and each XCD's tiles form one contiguous run.
@@ -173,6 +174,30 @@ static int check_ring_order() {
   return 0;
 }
 
+static int check_div24() {
+  // every numerator below 2^16 for every divisor up to 4200, then a sample
+  // of numerators up to 2^24
+  for (int d = 1; d <= 4200; ++d) {
+    const float inv = 1.0f / (float)d;
+    for (int e = 0; e < (1 << 16); ++e)
+      if (div24(e, d, inv) != e / d) {
+        std::printf("div24 %d / %d FAIL\n", e, d);
+        return 1;
+      }
+  }
+  std::mt19937 rng(7);
+  for (int t = 0; t < 20000000; ++t) {
+    const int d = 1 + (int)(rng() % ((1u << 24) - 1));
+    const int e = (int)(rng() % (1u << 24));
+    if (div24(e, d, 1.0f / (float)d) != e / d) {
+      std::printf("div24 %d / %d FAIL\n", e, d);
+      return 1;
+    }
+  }
+  std::printf("div24 ok\n");
+  return 0;
+}
+
 static int check_xcd_tiles() {
   const int shapes[][3] = {{1, 1, 1}, {16, 4, 64}, {7, 9, 130}, {33, 65, 65}, {256, 256, 256},
                            {17, 3, 200}, {512, 1024, 1024}};
@@ -220,5 +245,6 @@ int main() {
   if (check_candidates()) return 1;
   if (check_ring_order()) return 1;
   if (check_xcd_tiles()) return 1;
+  if (check_div24()) return 1;
   return 0;
 }
