@@ -269,16 +269,39 @@ constexpr int SP_T = 32;       // tile edge = MFMA block
 constexpr int SP_K = 16;       // samples per matrix product
 constexpr int SP_NK = 64;        // staging slots: one batch of candidates
 
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+
+// bf16(a) | bf16(b) << 16, round to nearest even: one packed conversion
+__device__ __forceinline__ unsigned bf16_pair(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){a, b}, v2bf));
+}
 __device__ __forceinline__ unsigned bf16_bits(float x) {
   return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)x);
 }
-// hi | lo << 16 with hi + lo ~ x to ~2^-17 (round-to-nearest conversions)
-__device__ __forceinline__ unsigned bf16_split(float x) {
-  const __bf16 h = (__bf16)x;
-  return bf16_bits(x) | (bf16_bits(x - (float)h) << 16);
-}
 __device__ __forceinline__ unsigned f16_bits(float x) {
   return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)x);
+}
+// f16(a w) | f16(b w) << 16, each product rounded once: mixed-precision
+// FMAs (float32 sources, zero addend) into the low and the high half
+__device__ __forceinline__ unsigned f16_prod_pair(float a, float b, float w) {
+  unsigned r;
+  asm("v_fma_mixlo_f16 %0, %1, %2, 0\n\tv_fma_mixhi_f16 %0, %3, %2, 0"
+      : "=&v"(r)
+      : "v"(a), "v"(w), "v"(b));
+  return r;
+}
+// hi | lo << 16 with hi + lo ~ x to ~2^-17 (round-to-nearest conversions);
+// hi is converted twice so that the final pair is one conversion of (x, lo)
+__device__ __forceinline__ unsigned bf16_split(float x) {
+  const float h = __uint_as_float(bf16_pair(x, x) << 16);
+  return bf16_pair(x, x - h);
+}
+// the splits of a complex value: (re hi | re lo << 16, im hi | im lo << 16)
+__device__ __forceinline__ uint2 bf16_split2(float re, float im) {
+  const unsigned hh = bf16_pair(re, im);
+  const float hre = __uint_as_float(hh << 16), him = __uint_as_float(hh & 0xFFFF0000u);
+  return make_uint2(bf16_pair(re, re - hre), bf16_pair(im, im - him));
 }
 __device__ __forceinline__ int med3i(int a, int lo, int hi) {
   int r;
@@ -421,14 +444,13 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
             for (int k = 0; k < W; ++k) {
               if constexpr (PREC == 0) {
                 st_a[pos * WS + 1 + k] = bf16_split(wy[k]);
-                st_b[pos * WS + 1 + k] =
-                    make_uint2(bf16_split(cur.c.x * wx[k]), bf16_split(cur.c.y * wx[k]));
+                st_b[pos * WS + 1 + k] = bf16_split2(cur.c.x * wx[k], cur.c.y * wx[k]);
               } else if constexpr (PREC == 1) {
                 st_a[pos * WS + 1 + k] = (unsigned short)f16_bits(wy[k]);
-                st_b[pos * WS + 1 + k] = f16_bits(cur.c.x * wx[k]) | (f16_bits(cur.c.y * wx[k]) << 16);
+                st_b[pos * WS + 1 + k] = f16_prod_pair(cur.c.x, cur.c.y, wx[k]);
               } else {
                 st_a[pos * WS + 1 + k] = (unsigned short)bf16_bits(wy[k]);
-                st_b[pos * WS + 1 + k] = bf16_bits(cur.c.x * wx[k]) | (bf16_bits(cur.c.y * wx[k]) << 16);
+                st_b[pos * WS + 1 + k] = bf16_pair(cur.c.x * wx[k], cur.c.y * wx[k]);
               }
             }
             st_l[pos] = (int)(((unsigned)(cur.ly * SA) & 0xFFFFu) | ((unsigned)(cur.lx * SB) << 16));
@@ -739,12 +761,16 @@ constexpr int X3_ZT = 2;
 constexpr int X3_ROWS = 32 * X3_ZT * X3_WAVES;  // rows per block
 
 __device__ __forceinline__ void split8(const float x[8], v8u& hi, v8u& lo) {
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  v4u h4, l4;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const unsigned s2 = bf16_split(x[t]);
-    hi[t] = (unsigned short)(s2 & 0xFFFFu);
-    lo[t] = (unsigned short)(s2 >> 16);
+  for (int t = 0; t < 8; t += 2) {
+    const unsigned hh = bf16_pair(x[t], x[t + 1]);
+    h4[t >> 1] = hh;
+    l4[t >> 1] = bf16_pair(x[t] - __uint_as_float(hh << 16), x[t + 1] - __uint_as_float(hh & 0xFFFF0000u));
   }
+  hi = __builtin_bit_cast(v8u, h4);
+  lo = __builtin_bit_cast(v8u, l4);
 }
 
 // A fragment of tile row `row` (clamped into the table) at K-step s
