@@ -931,13 +931,53 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float
 // one block forms f and 1/f (exact powers of two) in dyn[0], dyn[1].
 constexpr int ABSMAX_BLOCKS = 1024;
 
-__global__ __launch_bounds__(256) void k_absmax_partial(const void* __restrict__ x, size_t n, int dt,
+// largest magnitude among the elements of one 16-byte chunk
+template <int DT>
+__device__ __forceinline__ float absmax16(uint4 v) {
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+  float m = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if constexpr (DT == LAMINO_F32) {
+      m = fmaxf(m, fabsf(__uint_as_float(w[k])));
+    } else if constexpr (DT == LAMINO_BF16) {
+      m = fmaxf(m, fmaxf(fabsf(__uint_as_float(w[k] << 16)), fabsf(__uint_as_float(w[k] & 0xFFFF0000u))));
+    } else if constexpr (DT == LAMINO_F16) {
+      const float a = __half2float(__ushort_as_half((unsigned short)(w[k] & 0xFFFFu)));
+      const float b = __half2float(__ushort_as_half((unsigned short)(w[k] >> 16)));
+      m = fmaxf(m, fmaxf(fabsf(a), fabsf(b)));
+    } else if constexpr (DT == LAMINO_U16) {
+      m = fmaxf(m, (float)max(w[k] & 0xFFFFu, w[k] >> 16));
+    } else {
+      const unsigned b = max(max(w[k] & 0xFFu, (w[k] >> 8) & 0xFFu), max((w[k] >> 16) & 0xFFu, w[k] >> 24));
+      m = fmaxf(m, (float)b);
+    }
+  }
+  return m;
+}
+
+// 16-byte loads (four in flight per thread) when the input is 16-byte
+// aligned, element loads for the rest
+template <int DT>
+__global__ __launch_bounds__(256) void k_absmax_partial(const void* __restrict__ x, size_t n,
                                                          float* __restrict__ part) {
+  constexpr size_t PER = DT == LAMINO_F32 ? 4 : (DT == LAMINO_U8 ? 16 : 8);  // elements per chunk
   __shared__ float red[4];
   float m = 0.f;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    m = fmaxf(m, fabsf(ld_r(x, i, dt)));
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t nv = 0;
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    nv = n / PER;
+    const uint4* v = reinterpret_cast<const uint4*>(x);
+    size_t i = tid;
+    for (; i + 3 * stride < nv; i += 4 * stride) {
+      const uint4 a = v[i], b = v[i + stride], c = v[i + 2 * stride], d = v[i + 3 * stride];
+      m = fmaxf(m, fmaxf(fmaxf(absmax16<DT>(a), absmax16<DT>(b)), fmaxf(absmax16<DT>(c), absmax16<DT>(d))));
+    }
+    for (; i < nv; i += stride) m = fmaxf(m, absmax16<DT>(v[i]));
+  }
+  for (size_t i = nv * PER + tid; i < n; i += stride) m = fmaxf(m, fabsf(ld_r(x, i, DT)));
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -974,7 +1014,13 @@ static void input_factor(const KParams& kp, const void* x, size_t n, int dt, flo
   int nb = 0;
   if (x) {
     nb = (int)std::min<size_t>(ABSMAX_BLOCKS, std::max<size_t>(1, (n + 255) / 256));
-    hipLaunchKernelGGL(k_absmax_partial, dim3(nb), dim3(256), 0, s, x, n, dt, dyn + 2);
+    switch (dt) {
+      case LAMINO_F32: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F32>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
+      case LAMINO_F16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
+      case LAMINO_BF16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_BF16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
+      case LAMINO_U8: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U8>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
+      default: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
+    }
   }
   hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, dyn, nb, bound);
 }

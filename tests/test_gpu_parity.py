@@ -256,3 +256,42 @@ def test_float16_storage_keeps_range_at_full_size(scale):
     for b in (b_fwd, b_adj, b_fbp):
         assert bool(torch.isfinite(b).all())
     assert max(errs) < TOL_LOWP
+
+
+@pytest.mark.parametrize("where", ["first", "tail"])
+def test_float16_input_scan_every_data_type_and_alignment(where):
+    # The per-call input factor of float16 storage comes from a scan of the
+    # data's largest magnitude.  Integer counts 0..255 are exact in every data
+    # type, so the FBP must be bit-identical for all five input types and for
+    # 16-byte aligned and misaligned buffers; the largest count sits in the
+    # first element or in the ragged tail after the last whole 16-byte chunk
+    # (a scan that missed it would pick a different factor).
+    nz, n, nt, h, w = 16, 24, 21, 17, 29
+    total = nt * h * w  # 10353: not a multiple of 4, 8 or 16 elements
+    rng = np.random.default_rng(11)
+    flat = rng.integers(0, 100, total)
+    flat[0 if where == "first" else total - 1] = 255
+    tilt = np.deg2rad(30.0)
+
+    def device_view(name, offset):
+        if name == "bf16":
+            buf = torch.zeros(total + offset, dtype=torch.bfloat16, device=dev())
+            buf[offset:] = torch.from_numpy(flat.astype(np.float32)).to(dev()).to(torch.bfloat16)
+        else:
+            a = np.zeros(total + offset, {"f32": np.float32, "f16": np.float16, "u8": np.uint8,
+                                          "u16": np.uint16}[name])
+            a[offset:] = flat
+            buf = torch.from_numpy(a).to(dev())
+        return buf[offset:].view(nt, h, w)
+
+    ref = None
+    for name in ["f32", "f16", "bf16", "u8", "u16"]:
+        plan = Plan(nz, n, nt, h, w, tilt, data_dtype=name, storage_dtype="f16")
+        for offset in (0, 1):
+            view = device_view(name, offset)
+            print(f"  {name} offset {offset}: data_ptr % 16 = {view.data_ptr() % 16}", flush=True)
+            out = to_np(plan.fbp(view))
+            if ref is None:
+                ref = out
+                assert np.isfinite(ref).all() and np.abs(ref).max() > 0
+            assert np.array_equal(out, ref), (name, offset)
