@@ -295,3 +295,38 @@ def test_float16_input_scan_every_data_type_and_alignment(where):
                 ref = out
                 assert np.isfinite(ref).all() and np.abs(ref).max() > 0
             assert np.array_equal(out, ref), (name, offset)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_every_gaussian_half_width(storage):
+    # kernel_m = 2 .. 8 selects a separate gridding / interpolation kernel
+    # instance per storage type.  FBP and L against the exact FP64 sums,
+    # bounded by the Gaussian gridding error for oversampling R = N_g / n
+    # (Greengard & Lee 2004: decay exp(-pi M (R - 1/2) / R); the constant
+    # measured is ~0.7 at this R = 8/3 and 1.2-1.6 at R = 2 on the 256^3
+    # workload, the test allows 4) plus three unit
+    # roundoffs of the stored values (spectra, slab planes, weights): 2^-16
+    # for float32 (bf16 hi + lo products), 2^-11 float16, 2^-8 bfloat16.  While
+    # the Gaussian term dominates, the error must fall as M grows.
+    nz, n, nt, h, w = 16, 24, 20, 16, 24
+    phi = np.deg2rad(30.0)
+    g = Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=phi)
+    rng = np.random.default_rng(21)
+    vol = rng.standard_normal((nz, n, n))
+    data = rng.standard_normal((nt, h, w))
+    ref_fbp, ref_fwd = nudft.fbp(data, g), nudft.forward(vol, g)
+    u = {"f32": 2.0 ** -16, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}[storage]
+    prev = None
+    for M in range(2, 9):
+        plan = Plan(nz, n, nt, h, w, phi, storage_dtype=storage, kernel_m=M)
+        assert plan.info.kernel_m == M
+        R = plan.info.grid / n
+        gauss = 4.0 * np.exp(-np.pi * M * (R - 0.5) / R)
+        e_fbp = rel(to_np(plan.fbp(to_dev(data))), ref_fbp)
+        e_fwd = rel(to_np(plan.fwd(to_dev(vol))), ref_fwd)
+        print(f"  {storage} M={M} R={R:.2f}: fbp {e_fbp:.2e} fwd {e_fwd:.2e} bound {gauss + 3 * u:.2e}",
+              flush=True)
+        assert e_fbp < gauss + 3 * u and e_fwd < gauss + 3 * u
+        if prev is not None and gauss > 30 * u:
+            assert e_fbp < prev[0] and e_fwd < prev[1]
+        prev = (e_fbp, e_fwd)
