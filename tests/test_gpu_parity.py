@@ -330,3 +330,31 @@ def test_every_gaussian_half_width(storage):
         if prev is not None and gauss > 30 * u:
             assert e_fbp < prev[0] and e_fwd < prev[1]
         prev = (e_fbp, e_fwd)
+
+
+@pytest.mark.parametrize("pad_u, pad_v", [(1.0, 1.0), (1.5, 3.0), (4.0, 1.2)])
+def test_detector_padding_factors(pad_u, pad_v):
+    # h_p, w_p = smallest powers of two >= pad * (h, w): every transform
+    # length and the number of frequency slabs change with the factors
+    g, plan, f, d = _pair(12, 20, 15, 14, 22, 25, pad_u=pad_u, pad_v=pad_v)
+    g.pad_u, g.pad_v = pad_u, pad_v
+    assert (plan.info.w_p, plan.info.h_p) == (g.w_p, g.h_p)
+    print(f"pad ({pad_u}, {pad_v}): w_p {g.w_p} h_p {g.h_p}", flush=True)
+    ef = rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g))
+    ea = rel(to_np(plan.adj(to_dev(d))), nudft.adjoint(d, g))
+    eb = rel(to_np(plan.fbp(to_dev(d))), nudft.fbp(d, g))
+    print(f"  fwd {ef:.2e} adj {ea:.2e} fbp {eb:.2e}")
+    assert ef < TOL_F32 and ea < TOL_F32 and eb < TOL_F32
+
+
+@pytest.mark.parametrize("phi", [80.0, -85.0, 89.0])
+def test_steep_tilts(phi):
+    # near-vertical tilts: the slab planes' in-plane offset l sin(phi) / h_p
+    # reaches half the grid, so samples wrap into the periodic tile copies
+    g, plan, f, d = _pair(10, 18, 13, 12, 20, phi)
+    print(f"tilt {phi}", flush=True)
+    ef = rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g))
+    ea = rel(to_np(plan.adj(to_dev(d))), nudft.adjoint(d, g))
+    eb = rel(to_np(plan.fbp(to_dev(d))), nudft.fbp(d, g))
+    print(f"  fwd {ef:.2e} adj {ea:.2e} fbp {eb:.2e}")
+    assert ef < TOL_F32 and ea < TOL_F32 and eb < TOL_F32
