@@ -215,8 +215,10 @@ def cpu_direct_fbp(data_np, budget_s=5.0):
                       f"measured, {t_total:.0f} s extrapolated)"}
 
 
-def serving(dev, count, rate=20.0):
-    """Poisson stream of fp16-gridded FBP requests over three size classes."""
+def serving(dev, count, rate=20.0, host=False):
+    """Poisson stream of fp16-gridded FBP requests over three size classes;
+    host=True keeps the data in pinned host memory and returns every volume
+    to pinned host memory (latency from arrival to the result on the host)."""
     from paper_2401_11101_amd.serve import Server, run_poisson
 
     classes = []
@@ -225,8 +227,11 @@ def serving(dev, count, rate=20.0):
         ells = synth.random_ellipsoids(30, nz, n, seed=seed)
         d = synth.project_ellipsoids(ells, nt, h, w, np.deg2rad(30.0), device=dev, dtype=torch.float32)
         d = synth.add_noise(d, 0.005, seed=seed + 100).contiguous()
+        if host:
+            d = d.cpu().pin_memory()
         classes.append((nz, n, nt, h, w, d))
-    srv = Server(max_slots=4, hbm_budget=32 << 30, storage_dtype="f16", data_dtype="f32", device=dev)
+    srv = Server(max_slots=4, hbm_budget=32 << 30, storage_dtype="f16", data_dtype="f32", device=dev,
+                 result_on_host=host, keep_results=False)
     # warm every class once (plans, slots, kernels), then the timed stream
     run_poisson(srv, classes, rate=1000.0, count=6, seed=99)
     srv.finished.clear()
@@ -236,7 +241,8 @@ def serving(dev, count, rate=20.0):
             "p99_ms": round(st["p99_ms"], 3), "mean_ms": round(st["mean_ms"], 3),
             "throughput_rps": round(st["throughput_rps"], 3), "gvoxel_per_s": round(st["gvoxel_per_s"], 4),
             "classes": "U{128^3/180, 256^3/400, 512x512x256/720}, tilt U[20,40] deg, fp16 storage, "
-                       "4 slots, data resident on the device"}
+                       "4 slots, " + ("data in pinned host memory, volumes returned to pinned host memory"
+                                      if host else "data resident on the device")}
 
 
 def large_volume(dev, steps):
@@ -485,6 +491,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving stream (0 skips it)")
+    ap.add_argument("--serve-host", action="store_true",
+                    help="also run the serving stream with data and results in pinned host memory")
     ap.add_argument("--extra", action="store_true",
                     help="also time the 1024^2 x 512 volume, CGLS and the TV-regularised ADMM")
     ap.add_argument("--admm", action="store_true",
@@ -573,6 +581,9 @@ def main():
     if args.serve_requests:
         log(f"serving: {args.serve_requests} Poisson requests at 20/s")
         line["serving"] = serving(dev, args.serve_requests)
+        if args.serve_host:
+            log(f"serving from host memory: {args.serve_requests} Poisson requests at 20/s")
+            line["serving_host"] = serving(dev, args.serve_requests, host=True)
     if args.extra:
         log("timing the 1024^2 x 512 volume")
         line["large_volume"] = large_volume(dev, 3)

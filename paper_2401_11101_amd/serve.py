@@ -1,7 +1,10 @@
 """Continuous-batching FBP request server on one GPU.
 
-Requests (volume shape, angles, detector, tilt, device-resident data)
-arrive over time.  The server keeps a pool of execution slots; a slot owns
+Requests (volume shape, angles, detector, tilt, data) arrive over time.
+Data may be device-resident or in pinned host memory; host data are copied
+to the device on the request's slot stream, and with result_on_host the
+volume is copied back into pinned host memory on the same stream, so the
+measured latency then runs from arrival to the result on the host.  The server keeps a pool of execution slots; a slot owns
 a HIP stream (default priority) and a workspace sized for one shape class.
 A request is admitted as soon as a slot of its class is free or a new slot
 fits in the HBM budget; its FBP is enqueued on the slot's stream at once,
@@ -26,8 +29,8 @@ from .plan import Plan, _DTYPES, _FILTERS
 
 
 class Request:
-    __slots__ = ("rid", "shape", "tilt", "data", "arrival", "admitted", "done", "out", "event",
-                 "slot")
+    __slots__ = ("rid", "shape", "tilt", "data", "arrival", "admitted", "done", "out", "out_host",
+                 "event", "slot", "_dev_data")
 
     def __init__(self, rid, nz, n, n_theta, h, w, tilt, data, arrival=None):
         self.rid = rid
@@ -38,8 +41,10 @@ class Request:
         self.admitted = None
         self.done = None
         self.out = None
+        self.out_host = None
         self.event = None
         self.slot = None
+        self._dev_data = None
 
     @property
     def voxels(self):
@@ -60,16 +65,22 @@ class Server:
     """Admits FBP requests into per-class slots and runs them concurrently.
 
     max_slots bounds the number of concurrently running requests;
-    hbm_budget bounds the bytes of all slot workspaces (0: no bound)."""
+    hbm_budget bounds the bytes of all slot workspaces (0: no bound);
+    result_on_host copies every volume into pinned host memory (Request.out_host);
+    keep_results=False drops a request's volumes once it has finished (a stream
+    whose consumer only needs the timings keeps no outputs alive)."""
 
     def __init__(self, max_slots=4, hbm_budget=0, storage_dtype="f16", data_dtype="f32",
-                 filter="shepp-logan", device=None, plan_cache=64):
+                 filter="shepp-logan", device=None, plan_cache=64, result_on_host=False,
+                 keep_results=True):
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         self.max_slots = max_slots
         self.hbm_budget = hbm_budget
         self.storage_dtype = storage_dtype
         self.data_dtype = data_dtype
         self.filter = filter
+        self.result_on_host = result_on_host
+        self.keep_results = keep_results
         self.slots = []
         self.queue = collections.deque()
         self.finished = []
@@ -109,6 +120,8 @@ class Server:
 
     # ------------------------------------------------------------ admission
     def submit(self, req):
+        if req.data.device.type == "cpu" and not req.data.is_pinned():
+            raise ValueError(f"request {req.rid}: host data must be in pinned memory")
         self.queue.append(req)
         self._admit()
 
@@ -157,10 +170,18 @@ class Server:
                               ctypes.c_void_p(stream.cuda_stream))
         nz, n = req.shape[0], req.shape[1]
         with torch.cuda.stream(stream):
+            if req.data.device.type == "cpu":  # pinned (checked at submission)
+                req._dev_data = req.data.to(self.device, non_blocking=True)
+            else:
+                req._dev_data = req.data
+                req.data.record_stream(stream)
             req.out = torch.empty((nz, n, n), dtype=torch.float32, device=self.device)
-        req.data.record_stream(stream)
-        _abi.lamino_fbp(h, ctypes.c_void_p(req.data.data_ptr()), ctypes.c_void_p(req.out.data_ptr()),
+        _abi.lamino_fbp(h, ctypes.c_void_p(req._dev_data.data_ptr()), ctypes.c_void_p(req.out.data_ptr()),
                         ctypes.c_void_p(stream.cuda_stream))
+        if self.result_on_host:
+            req.out_host = torch.empty((nz, n, n), dtype=torch.float32, pin_memory=True)
+            with torch.cuda.stream(stream):
+                req.out_host.copy_(req.out, non_blocking=True)
         req.event = torch.cuda.Event()
         req.event.record(stream)
         req.admitted = time.perf_counter()
@@ -175,6 +196,9 @@ class Server:
             r = s.busy
             if r is not None and r.event.query():
                 r.done = time.perf_counter()
+                r._dev_data = None
+                if not self.keep_results:
+                    r.out = r.out_host = None
                 s.busy = None
                 self.finished.append(r)
                 n += 1

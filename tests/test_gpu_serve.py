@@ -67,3 +67,37 @@ def test_poisson_stream_reports_latency():
     print(st)
     assert st["requests"] == 40 and st["p99_ms"] >= st["p50_ms"] > 0
     srv.close()
+
+
+def test_host_resident_requests_match_device_resident():
+    # data in pinned host memory, volumes returned to pinned host memory:
+    # the copies run on each request's slot stream, the results equal those
+    # of device-resident requests bit for bit, and unpinned host data are
+    # refused before anything is enqueued
+    reqs_dev, reqs_host = [], []
+    srv_d = Server(max_slots=3, storage_dtype="f16")
+    srv_h = Server(max_slots=3, storage_dtype="f16", result_on_host=True)
+    for i in range(9):
+        cls = CLASSES[i % 3]
+        tilt = np.deg2rad(22 + i)
+        d = _data(cls, 200 + i)
+        rd = Request(i, *cls, tilt, d)
+        rh = Request(i, *cls, tilt, d.cpu().pin_memory())
+        reqs_dev.append(rd)
+        reqs_host.append(rh)
+        srv_d.submit(rd)
+        srv_h.submit(rh)
+        srv_d.poll()
+        srv_h.poll()
+    srv_d.drain()
+    srv_h.drain()
+    torch.cuda.synchronize()
+    for rd, rh in zip(reqs_dev, reqs_host):
+        assert rh.out_host is not None and rh.out_host.device.type == "cpu" and rh.out_host.is_pinned()
+        assert torch.equal(rh.out_host, rd.out.cpu()), rd.rid
+        assert rh.done >= rh.arrival
+    with pytest.raises(ValueError):
+        srv_h.submit(Request(99, *CLASSES[0], 0.4, _data(CLASSES[0], 7).cpu()))
+    assert not srv_h.queue
+    srv_d.close()
+    srv_h.close()
