@@ -4,8 +4,10 @@ Requests (volume shape, angles, detector, tilt, data) arrive over time.
 Data may be device-resident or in pinned host memory; host data are copied
 to the device on the request's slot stream, and with result_on_host the
 volume is copied back into pinned host memory on the same stream, so the
-measured latency then runs from arrival to the result on the host.  The server keeps a pool of execution slots; a slot owns
-a HIP stream (default priority) and a workspace sized for one shape class.
+measured latency then runs from arrival to the result on the host.
+
+The server keeps a pool of execution slots; a slot owns a HIP stream
+(default priority) and a workspace sized for one shape class.
 A request is admitted as soon as a slot of its class is free or a new slot
 fits in the HBM budget; its FBP is enqueued on the slot's stream at once,
 so requests that arrive while others run overlap on the device.  Geometry
