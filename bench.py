@@ -491,8 +491,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="requests of the serving stream (0 skips it)")
-    ap.add_argument("--serve-host", action="store_true",
-                    help="also run the serving stream with data and results in pinned host memory")
+    ap.add_argument("--no-serve-host", action="store_true",
+                    help="skip the serving stream with data and results in pinned host memory")
     ap.add_argument("--extra", action="store_true",
                     help="also time the 1024^2 x 512 volume, CGLS and the TV-regularised ADMM")
     ap.add_argument("--admm", action="store_true",
@@ -581,7 +581,7 @@ def main():
     if args.serve_requests:
         log(f"serving: {args.serve_requests} Poisson requests at 20/s")
         line["serving"] = serving(dev, args.serve_requests)
-        if args.serve_host:
+        if not args.no_serve_host:
             log(f"serving from host memory: {args.serve_requests} Poisson requests at 20/s")
             line["serving_host"] = serving(dev, args.serve_requests, host=True)
     if args.extra:
