@@ -358,3 +358,27 @@ def test_steep_tilts(phi):
     eb = rel(to_np(plan.fbp(to_dev(d))), nudft.fbp(d, g))
     print(f"  fwd {ef:.2e} adj {ea:.2e} fbp {eb:.2e}")
     assert ef < TOL_F32 and ea < TOL_F32 and eb < TOL_F32
+
+
+def test_largest_fft_sizes_adjoint_and_chunking():
+    # the largest transforms the plan accepts: detector rows padded to
+    # w_p = 4096 and slab grids of N_g = 4096 (n = 2048).  The exact sums are
+    # out of reach at this size, so the check is the adjoint identity
+    # <L f, d> = <f, L* d> in FP64 and chunked == unchunked.
+    nz, n, nt, h, w = 4, 2048, 6, 6, 2048
+    tilt = np.deg2rad(30.0)
+    plan = Plan(nz, n, nt, h, w, tilt)
+    assert (plan.info.w_p, plan.info.grid) == (4096, 4096)
+    print(f"max sizes: w_p {plan.info.w_p}, grid {plan.info.grid}", flush=True)
+    gen = torch.Generator(device=dev()).manual_seed(3)
+    f = torch.rand((nz, n, n), device=dev(), generator=gen) - 0.5
+    d = torch.rand((nt, h, w), device=dev(), generator=gen) - 0.5
+    lf, ld = plan.fwd(f), plan.adj(d)
+    a = float((lf.double() * d.double()).sum())
+    b = float((f.double() * ld.double()).sum())
+    scale = float(lf.double().norm() * d.double().norm())
+    print(f"  <Lf,d> {a:.6e} <f,L*d> {b:.6e} |diff|/(|Lf||d|) {abs(a - b) / scale:.2e}", flush=True)
+    assert abs(a - b) <= 1e-5 * scale
+    small = Plan(nz, n, nt, h, w, tilt, z_chunk=3, slab_chunk=1, theta_chunk=4)
+    assert rel(to_np(small.adj(d)), to_np(ld)) < 1e-6
+    assert rel(to_np(small.fwd(f)), to_np(lf)) < 1e-6
