@@ -57,7 +57,8 @@ def forward_spectra(f, geom):
     ms = freqs(geom.w_p)
     E = x3_phases(geom, -1.0)
     # inner integral of eq:fftfwdsplit: sum over x3 for every (l, x2, x1)
-    ghat = np.einsum("zl,zyx->lyx", E, f, optimize=True)
+    # (contiguous per slab, so that the products below run through BLAS)
+    ghat = np.ascontiguousarray(np.einsum("zl,zyx->lyx", E, f, optimize=True))
     A = np.empty((geom.n_theta, len(ls), len(ms)), dtype=np.complex128)
     for li, l in enumerate(ls):
         P1, P2 = _phases(geom, l, -1.0)
