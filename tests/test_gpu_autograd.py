@@ -70,4 +70,8 @@ def test_cgls_tracks_fp64_oracle_and_residual_decreases():
                    np.zeros_like(f), iters)
     e = rel(to_np(x), ref)
     print(f"CGLS {iters} iterations vs FP64 oracle: rel-L2 {e:.2e}; residual {res[0]:.3e} -> {res[-1]:.3e}")
-    assert e < 1e-3
+    # the float32 operators sit ~5e-6 from the exact ones (Gaussian USFFT,
+    # M = 5, and bf16 hi + lo matrix-core products); 8 CG steps on this
+    # well-posed instance keep the iterate within the 1e-4 bar of the
+    # float32 operators themselves
+    assert e < 1e-4

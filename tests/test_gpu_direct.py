@@ -141,3 +141,38 @@ def test_fourier_fbp_accepts_8bit_data_and_rejects_8bit_forward():
         p8.fwd(torch.zeros(p8.shape_vol, device=dev()), out=torch.empty(p8.shape_data, dtype=torch.uint8,
                                                                           device=dev()))
     assert e.value.code == _abi.LAMINO_E_INVALID
+
+
+def test_fourier_fbp_against_direct_fbp_triangle():
+    # The 64^3 configuration (64 angles on [0, 2 pi), tilt 30 deg, detector
+    # 64 x 64, 20 ellipsoids, 1% noise, Shepp-Logan).  The Fourier-route FBP
+    # and the direct (bilinear) FBP are two discretisations of eq:recon; their
+    # gap is a property of the discretisations, measured oracle against
+    # oracle: g_O = |O2 - O1| / |O1| (O2 the exact Fourier sums, O1 the
+    # direct FBP).  The GPU's Fourier FBP must show the same gap to the
+    # direct FBP within its own distance to O2 (triangle inequality), and the
+    # GPU's direct FBP must match O1.
+    from oracle import nudft
+
+    print("Fourier vs direct FBP, 64^3 configuration", flush=True)
+    g, _, d = ellipsoid_data(20, 64, 64, 64, 64, 64, np.deg2rad(30), 0.01)
+    d32 = d.astype(np.float32)
+    d64 = d32.astype(np.float64)
+    plan = Plan(64, 64, 64, 64, 64, g.phi)
+    four = to_np(plan.fbp(to_dev(d32)))
+    dirg = to_np(plan.direct_fbp(to_dev(d32)))
+    o2 = nudft.fbp(d64, g, filters.SHEPP_LOGAN)
+    o1 = direct.fbp(d64, g, filters.SHEPP_LOGAN)
+    n1 = np.linalg.norm(o1)
+    gap_oracle = np.linalg.norm(o2 - o1) / n1
+    gap_gpu = np.linalg.norm(four - dirg) / np.linalg.norm(dirg)
+    gap_gpu_o1 = np.linalg.norm(four - o1) / n1
+    d_four = np.linalg.norm(four - o2) / n1
+    d_dir = np.linalg.norm(dirg - o1) / n1
+    print(f"  |O2 - O1|/|O1| {gap_oracle:.4e}; |GPU Fourier - GPU direct|/|GPU direct| {gap_gpu:.4e}; "
+          f"|GPU Fourier - O1|/|O1| {gap_gpu_o1:.4e}")
+    print(f"  |GPU Fourier - O2|/|O1| {d_four:.2e}; |GPU direct - O1|/|O1| {d_dir:.2e}")
+    assert d_four < 1e-4 * np.linalg.norm(o2) / n1
+    assert d_dir < TOL_DIR_FBP
+    assert abs(gap_gpu_o1 - gap_oracle) <= d_four * (1 + 1e-9)
+    assert abs(gap_gpu - gap_oracle) <= d_four + 2 * d_dir + 1e-12

@@ -300,17 +300,42 @@ def test_full_size_subproblem_decreases_and_dual_is_feasible():
     assert F[0] > F[1] > F[2]
 
 
-@pytest.mark.parametrize("storage, bar", [("f16", 1e-2), ("bf16", 5e-2)])
-def test_admm_with_16bit_storage_matches_oracle(storage, bar):
-    # The 16-bit operators differ from the exact ones by 2.9e-4 (f16) and
-    # 1.2e-3 (bf16) on this instance; the float32 run shows the 3 x 3
-    # iterations amplifying operator error about tenfold (3e-6 -> 3e-5), so
-    # mu is held to ~3x that estimate.  psi and lambda, which threshold
-    # gradient differences, are reported.
+def _operator_error(storage, mu_ref):
+    """Relative L2 distance of the plan's L and L* from the exact sums on this
+    instance: L on the oracle's final iterate, L* on the data."""
+    g, d32 = _problem()
+    plan = Plan(NZ, N, NT, H, W, PHI, storage_dtype=storage)
+    ef = rel(to_np(plan.fwd(to_dev(mu_ref))), nudft.forward(mu_ref, g))
+    ea = rel(to_np(plan.adj(to_dev(d32))), nudft.adjoint(d32.astype(np.float64), g))
+    return max(ef, ea)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_admm_with_16bit_storage_matches_oracle(storage):
+    # Error model (first-order perturbation of the ADMM map): after a fixed
+    # number of iterations each iterate x_i (mu, psi, lambda) is displaced from
+    # the exact-operator iterate by kappa_i eps, where eps is the relative
+    # error of the operators the iterations run with and kappa_i the
+    # amplification of iterate i by the 3 x 3 iterations on this instance.
+    # kappa_i is measured on the float32 run (its own operator error eps_32
+    # measured the same way); the 16-bit run must then satisfy
+    # e_i <= 3 kappa_i eps_16 for all three iterates, the factor 3 allowing
+    # for second-order terms and for voxels that cross the shrink threshold.
+    # Rounding inside the float32 loop only raises kappa_i (a looser bar).
     print(f"admm {storage} storage", flush=True)
-    mu, psi, lam = _gpu(0.1, 1.0, 3, 3, storage=storage)
     mu_o, psi_o, lam_o = _oracle(0.1, 1.0, 3, 3, None)
-    e = (rel(mu, mu_o), rel(psi, psi_o), rel(lam, lam_o))
-    print(f"  rel-L2 mu {e[0]:.2e} psi {e[1]:.2e} lambda {e[2]:.2e}")
-    assert np.all(np.isfinite(mu)) and np.all(np.isfinite(lam))
-    assert e[0] < bar
+    mu32, psi32, lam32 = _gpu(0.1, 1.0, 3, 3)
+    e32 = np.array([rel(mu32, mu_o), rel(psi32, psi_o), rel(lam32, lam_o)])
+    eps32 = _operator_error("f32", mu_o)
+    kappa = e32 / eps32
+    mu, psi, lam = _gpu(0.1, 1.0, 3, 3, storage=storage)
+    e = np.array([rel(mu, mu_o), rel(psi, psi_o), rel(lam, lam_o)])
+    eps = _operator_error(storage, mu_o)
+    bars = 3.0 * kappa * eps
+    print(f"  operator error f32 {eps32:.2e}, {storage} {eps:.2e}; amplification mu {kappa[0]:.1f} "
+          f"psi {kappa[1]:.1f} lambda {kappa[2]:.1f}")
+    print(f"  rel-L2 mu {e[0]:.2e} psi {e[1]:.2e} lambda {e[2]:.2e}; bars {bars[0]:.2e} "
+          f"{bars[1]:.2e} {bars[2]:.2e}")
+    assert np.all(np.isfinite(mu)) and np.all(np.isfinite(psi)) and np.all(np.isfinite(lam))
+    assert np.all(e32 < TOL_ADMM)
+    assert np.all(e <= bars)
