@@ -97,7 +97,12 @@ typedef struct {
   int z_chunk;        /* x3-transform output slices per launch; 0 = nz         */
   int slab_chunk;     /* frequency slabs gridded per pass; 0 = automatic       */
   int theta_chunk;    /* projections per detector-FFT pass; 0 = automatic      */
-  size_t hbm_budget;  /* max workspace bytes; 0 = no limit                    */
+  size_t hbm_budget;  /* max workspace bytes; 0 = no limit.  Chunks shrink to
+                         fit; if the device-resident workspace still exceeds
+                         the budget, the slab planes g and then also the
+                         spectra D are kept in a caller-owned host buffer
+                         (lamino_plan_host_sizes / lamino_plan_bind_host)
+                         and streamed through double-buffered device chunks */
 } lamino_opts;
 
 /* Derived sizes of a plan (read-only description). */
@@ -123,6 +128,12 @@ typedef struct {
                            [0.5, 1) (a scan of the input, undone at the
                            output): float16 intermediates stay in range for
                            any input scale                                    */
+  int spill_spectra;  /* 1: D lives in the host buffer (out-of-core plan)     */
+  int spill_slabs;    /* 1: g lives in the host buffer                        */
+  int col_chunk;      /* x3 columns per chunk when g lives in host memory     */
+  int io_z;           /* volume slices per chunk of lamino_fbp_host           */
+  size_t host_bytes;  /* host buffer bytes (0: everything on the device)      */
+  size_t io_bytes;    /* device staging bytes of lamino_fbp_host              */
 } lamino_info;
 
 /* Fill *opts with defaults (F32 data and storage, Shepp-Logan, pad 2). */
@@ -151,11 +162,59 @@ int lamino_plan_info(const lamino_plan_t* plan, lamino_info* info);
  * allowed.  Errors: E_INVALID (NULL/misaligned buffers), E_HIP. */
 int lamino_plan_bind(lamino_plan_t* plan, void* d_tables, void* d_work, void* stream);
 
+/* Host memory of an out-of-core plan (Section "GPU acceleration of
+ * reconstruction": chunks streamed between host and device memory on
+ * separate streams, transfers overlapping compute).  *host_bytes: bytes of
+ * the caller-owned host buffer that holds the spectra D[l][theta][k] and / or
+ * the slab planes g[l][y][x] when the device workspace alone exceeds
+ * opts.hbm_budget (0 for a device-resident plan).  *io_bytes: bytes of the
+ * device staging buffer lamino_fbp_host needs (data and volume chunks).
+ * Either pointer may be NULL.  Host-only. */
+int lamino_plan_host_sizes(const lamino_plan_t* plan, size_t* host_bytes, size_t* io_bytes);
+
+/* Attach the caller-owned host buffer of host_bytes bytes (256-byte
+ * aligned; pinned memory, e.g. hipHostMalloc, for transfers that overlap
+ * compute).  Required before any call on a plan with host_bytes > 0, and
+ * must outlive those calls; no HIP call.  Errors: E_INVALID. */
+int lamino_plan_bind_host(lamino_plan_t* plan, void* h_spill);
+
+/* Copy the plan's table image (table_bytes bytes: the per-angle
+ * trigonometry, filters, psi correction, x3 phases and twiddles computed in
+ * double precision by lamino_plan) into caller host memory host_dst of
+ * `bytes` >= table_bytes bytes, typically pinned memory from which the
+ * caller uploads it asynchronously on its own stream.  Host-only.
+ * Errors: E_INVALID (NULL argument, bytes too small). */
+int lamino_plan_table_image(const lamino_plan_t* plan, void* host_dst, size_t bytes);
+
+/* Attach caller-owned device buffers without uploading anything (no HIP
+ * call): d_tables must hold this plan's table image by the time a later
+ * call on the plan runs, e.g. through a copy from lamino_plan_table_image's
+ * output enqueued earlier on the call's stream.  Same buffer rules as
+ * lamino_plan_bind; this is the non-blocking form of binding for request
+ * loops that re-bind one workspace to many plans.  Errors: E_INVALID. */
+int lamino_plan_attach(lamino_plan_t* plan, void* d_tables, void* d_work);
+
 /* Filtered backprojection (eq:recon via eq:fftadj): vol = L*(W d).
  * d_data: device d[n_theta][h][w] in data_dtype (read only);
  * d_vol: device float vol[nz][n][n] (written).  Errors: E_INVALID,
  * E_UNBOUND, E_HIP. */
 int lamino_fbp(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
+/* Filtered backprojection with the data and the volume in host memory,
+ * for volumes or inputs larger than the device can hold: projection chunks
+ * (theta_chunk at a time) are copied in, the volume leaves in chunks of
+ * io_z slices (or, when the plan keeps g in host memory, in column chunks
+ * of all slices), each through two alternating device buffers of the
+ * caller-owned staging buffer d_io (io_bytes, 256-byte aligned), with the
+ * copies on two library-owned streams (default priority) overlapping the
+ * kernels on `stream`.  h_data: host d[n_theta][h][w] in data_dtype;
+ * h_vol: host float vol[nz][n][n] (written); both should be pinned.  The
+ * results equal lamino_fbp's.  When the call's work on `stream` is
+ * complete, h_vol is written.  With float16 storage the data are read
+ * twice (a scan for the input factor, then the transforms).  Errors as
+ * lamino_fbp. */
+int lamino_fbp_host(const lamino_plan_t* plan, const void* h_data, float* h_vol, void* d_io,
+                    void* stream);
 
 /* Filtered backprojection of raw detector counts.  The recording model of
  * Section "Laminography reconstruction" (the paragraph after eq:fwd),
@@ -188,7 +247,7 @@ int lamino_fbp_slices(const lamino_plan_t* plan, const void* d_data, double cent
 /* Forward projection (eq:fwd via eq:fftfwd): d = L vol.
  * d_vol: device float vol[nz][n][n] (read only); d_data: device
  * d[n_theta][h][w] in data_dtype (written; E_INVALID for integer data).
- * Errors as lamino_fbp. */
+ * Errors as lamino_fbp, and E_UNSUPPORTED for an out-of-core plan. */
 int lamino_fwd(const lamino_plan_t* plan, const float* d_vol, void* d_data, void* stream);
 
 /* Adjoint (eq:adj via eq:fftadj): vol = L* d, the exact transpose of

@@ -25,6 +25,11 @@ EXPORTED = (
     "lamino_plan_sizes",
     "lamino_plan_info",
     "lamino_plan_bind",
+    "lamino_plan_host_sizes",
+    "lamino_plan_bind_host",
+    "lamino_fbp_host",
+    "lamino_plan_table_image",
+    "lamino_plan_attach",
     "lamino_fbp",
     "lamino_fbp_raw",
     "lamino_fbp_slices",
@@ -92,6 +97,12 @@ class lamino_info(ctypes.Structure):
         ("off_slabs", ctypes.c_size_t),
         ("bytes_slabs", ctypes.c_size_t),
         ("spectra_scale", ctypes.c_double),
+        ("spill_spectra", ctypes.c_int),
+        ("spill_slabs", ctypes.c_int),
+        ("col_chunk", ctypes.c_int),
+        ("io_z", ctypes.c_int),
+        ("host_bytes", ctypes.c_size_t),
+        ("io_bytes", ctypes.c_size_t),
     ]
 
 
@@ -123,6 +134,11 @@ def load_library(path=LIB_PATH):
     lib.lamino_plan_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
     lib.lamino_plan_info.argtypes = [P, ctypes.POINTER(lamino_info)]
     lib.lamino_plan_bind.argtypes = [P, P, P, P]
+    lib.lamino_plan_table_image.argtypes = [P, P, ctypes.c_size_t]
+    lib.lamino_plan_host_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+    lib.lamino_plan_bind_host.argtypes = [P, P]
+    lib.lamino_fbp_host.argtypes = [P, P, P, P, P]
+    lib.lamino_plan_attach.argtypes = [P, P, P]
     lib.lamino_fbp.argtypes = [P, P, P, P]
     lib.lamino_fwd.argtypes = [P, P, P, P]
     lib.lamino_adj.argtypes = [P, P, P, P]
@@ -146,6 +162,8 @@ def load_library(path=LIB_PATH):
     lib.lamino_admm_tv_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.lamino_admm_tv.argtypes = [P, P, P, D, D, I, I, I, P, P]
     for name in ("lamino_plan", "lamino_plan_sizes", "lamino_plan_info", "lamino_plan_bind",
+                 "lamino_plan_table_image", "lamino_plan_attach", "lamino_plan_host_sizes",
+                 "lamino_plan_bind_host", "lamino_fbp_host",
                  "lamino_fbp", "lamino_fwd", "lamino_adj", "lamino_plan_destroy",
                  "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
                  "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink", "lamino_direct_work_bytes",
@@ -188,6 +206,30 @@ def lamino_plan_info(plan):
 
 def lamino_plan_bind(plan, d_tables, d_work, stream):
     _check(load_library().lamino_plan_bind(plan, d_tables, d_work, stream), "lamino_plan_bind")
+
+
+def lamino_plan_host_sizes(plan):
+    """(host_bytes, io_bytes) of an out-of-core plan."""
+    hb, io = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().lamino_plan_host_sizes(plan, ctypes.byref(hb), ctypes.byref(io)),
+           "lamino_plan_host_sizes")
+    return hb.value, io.value
+
+
+def lamino_plan_bind_host(plan, h_spill):
+    _check(load_library().lamino_plan_bind_host(plan, h_spill), "lamino_plan_bind_host")
+
+
+def lamino_fbp_host(plan, h_data, h_vol, d_io, stream):
+    _check(load_library().lamino_fbp_host(plan, h_data, h_vol, d_io, stream), "lamino_fbp_host")
+
+
+def lamino_plan_table_image(plan, host_dst, nbytes):
+    _check(load_library().lamino_plan_table_image(plan, host_dst, nbytes), "lamino_plan_table_image")
+
+
+def lamino_plan_attach(plan, d_tables, d_work):
+    _check(load_library().lamino_plan_attach(plan, d_tables, d_work), "lamino_plan_attach")
 
 
 def lamino_fbp(plan, d_data, d_vol, stream):
@@ -284,3 +326,4 @@ def lamino_strerror(code):
 
 def lamino_last_error():
     return load_library().lamino_last_error().decode()
+

@@ -55,24 +55,89 @@ constexpr int kAbsmaxBlocks = 1024;          // partial maxima of the float16 in
 
 void layout_work(lamino_plan_s* p) {
   const size_t sb = lam::storage_bytes(p->opts.storage_dtype);
+  const size_t ncol = (size_t)p->n * p->n;
   p->bytes_w1 = (size_t)p->theta_chunk * p->n_slab * p->w * 8;
   p->bytes_D = (size_t)p->n_slab * p->n_theta * p->w_p * sb;
   p->bytes_G = (size_t)p->slab_chunk * p->grid * p->grid * 8;
-  p->bytes_g = (size_t)p->n_slab * p->n * p->n * sb;
+  p->bytes_g = (size_t)p->n_slab * ncol * sb;
   size_t off = 0;
-  p->off_w1 = off;
-  off += align256(p->bytes_w1);
-  p->off_D = off;
-  off += align256(p->bytes_D);
-  p->off_G = off;
-  off += align256(p->bytes_G);
-  p->off_g = off;
-  off += align256(p->bytes_g);
-  p->off_phase = off;  // rotation-axis phase ramp, w_p complex values
-  off += align256((size_t)p->w_p * 8);
-  p->off_dyn = off;    // float16 per-call input factor and block partial maxima
-  off += align256((size_t)(2 + kAbsmaxBlocks) * 4);
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  p->off_w1 = take(p->bytes_w1);
+  p->off_D = 0;
+  if (!p->spill_D) {
+    p->off_D = take(p->bytes_D);
+  } else {
+    for (int i = 0; i < 2; ++i) p->off_Dout[i] = take((size_t)p->n_slab * p->theta_chunk * p->w_p * sb);
+    for (int i = 0; i < 2; ++i) p->off_Din[i] = take((size_t)p->slab_chunk * p->n_theta * p->w_p * sb);
+  }
+  p->off_G = take(p->bytes_G);
+  p->off_g = 0;
+  if (!p->spill_g) {
+    p->off_g = take(p->bytes_g);
+  } else {
+    for (int i = 0; i < 2; ++i) p->off_gout[i] = take((size_t)p->slab_chunk * ncol * sb);
+    for (int i = 0; i < 2; ++i) p->off_gcol[i] = take((size_t)p->n_slab * p->col_chunk * sb);
+  }
+  p->off_phase = take((size_t)p->w_p * 8);  // rotation-axis phase ramp, w_p complex values
+  // float16 per-call input factor and block partial maxima
+  p->off_dyn = take((size_t)(2 + kAbsmaxBlocks) * 4);
   p->work_bytes = off;
+  // host spill buffer
+  size_t h = 0;
+  p->off_hD = p->off_hg = 0;
+  if (p->spill_D) {
+    p->off_hD = h;
+    h += align256(p->bytes_D);
+  }
+  if (p->spill_g) {
+    p->off_hg = h;
+    h += align256(p->bytes_g);
+  }
+  p->host_bytes = h;
+  // staging buffer of lamino_fbp_host
+  size_t io = 0;
+  for (int i = 0; i < 2; ++i) {
+    p->off_in[i] = io;
+    io += align256((size_t)p->theta_chunk * p->h * p->w * lam::data_bytes(p->opts.data_dtype));
+  }
+  for (int i = 0; i < 2; ++i) {
+    p->off_vout[i] = io;
+    io += align256(p->spill_g ? (size_t)p->nz * p->col_chunk * 4 : (size_t)p->io_z * ncol * 4);
+  }
+  p->io_bytes = io;
+}
+
+// Halve the chunk whose buffers take the most workspace until the layout fits
+// `budget` or every chunk is down to one unit; returns whether it fits.
+bool shrink_to_budget(lamino_plan_s* p, size_t budget) {
+  const size_t sb = lam::storage_bytes(p->opts.storage_dtype);
+  const size_t ncol = (size_t)p->n * p->n;
+  layout_work(p);
+  while (p->work_bytes > budget) {
+    const size_t by_theta = p->bytes_w1 + (p->spill_D ? 2 * (size_t)p->n_slab * p->theta_chunk * p->w_p * sb : 0);
+    const size_t by_slab = p->bytes_G + (p->spill_D ? 2 * (size_t)p->slab_chunk * p->n_theta * p->w_p * sb : 0) +
+                           (p->spill_g ? 2 * (size_t)p->slab_chunk * ncol * sb : 0);
+    const size_t by_col = p->spill_g ? 2 * (size_t)p->n_slab * p->col_chunk * sb : 0;
+    if (p->slab_chunk > 1 && by_slab >= by_theta && by_slab >= by_col) {
+      p->slab_chunk = (p->slab_chunk + 1) / 2;
+    } else if (p->theta_chunk > 1 && by_theta >= by_col) {
+      p->theta_chunk = (p->theta_chunk + 1) / 2;
+    } else if (p->spill_g && p->col_chunk > 256) {
+      p->col_chunk = std::max(256, p->col_chunk / 2 / 256 * 256);
+    } else if (p->slab_chunk > 1) {
+      p->slab_chunk = (p->slab_chunk + 1) / 2;
+    } else if (p->theta_chunk > 1) {
+      p->theta_chunk = (p->theta_chunk + 1) / 2;
+    } else {
+      return false;
+    }
+    layout_work(p);
+  }
+  return true;
 }
 
 int round_up(int a, int b) { return (a + b - 1) / b * b; }
@@ -216,11 +281,23 @@ void build_tables(lamino_plan_s* p) {
 
 namespace lam {
 
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
 size_t storage_bytes(int dtype) { return dtype == LAMINO_F32 ? 8 : 4; }
 size_t data_bytes(int dtype) { return dtype == LAMINO_F32 ? 4 : (dtype == LAMINO_U8 ? 1 : 2); }
 bool integer_dtype(int dtype) { return dtype == LAMINO_U8 || dtype == LAMINO_U16; }
 
-KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
+KParams make_params(const lamino_plan_s* p, bool fbp_filter, const void* tables, void* work) {
+  if (!tables) tables = p->d_tables;
+  if (!work) work = p->d_work;
   KParams k;
   k.nz = p->nz;
   k.n = p->n;
@@ -241,7 +318,7 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   k.gs = (float)((double)p->grid * std::sin(p->tilt) / p->h_p);
   k.data_dtype = p->opts.data_dtype;
   k.storage_dtype = p->opts.storage_dtype;
-  const char* t = static_cast<const char*>(p->d_tables);
+  const char* t = static_cast<const char*>(tables);
   k.trig = reinterpret_cast<const float2*>(t + p->off_trig);
   k.filt = reinterpret_cast<const float*>(t + (fbp_filter ? p->off_filt_fbp : p->off_filt_adj));
   k.deapod = reinterpret_cast<const float*>(t + p->off_deapod);
@@ -255,7 +332,7 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
     // kept below 2^15 by 2^15 / 2^ceil(log2(32 n^2))
     k.fwd_g_scale = (float)(1.0 / pow2_at_least(p->nz));
     k.fwd_D_scale = (float)(32768.0 / pow2_at_least(32.0 * p->n * p->n));
-    k.dyn = reinterpret_cast<const float*>(static_cast<const char*>(p->d_work) + p->off_dyn);
+    k.dyn = reinterpret_cast<const float*>(static_cast<const char*>(work) + p->off_dyn);
   } else {
     k.fwd_g_scale = 1.f;
     k.fwd_D_scale = 1.f;
@@ -276,6 +353,16 @@ KParams make_params(const lamino_plan_s* p, bool fbp_filter) {
   return k;
 }
 
+hipError_t ensure_pipe(lamino_plan_s* p) {
+  if (p->pipe_ready) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&p->s_in, hipStreamNonBlocking);  // default priority
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->s_out, hipStreamNonBlocking);
+  for (auto& ev : p->ev)
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) p->pipe_ready = true;
+  return e;
+}
+
 static hipEvent_t take_event(lamino_plan_s* p) {
   if (!p->event_pool.empty()) {
     hipEvent_t e = p->event_pool.back();
@@ -287,10 +374,11 @@ static hipEvent_t take_event(lamino_plan_s* p) {
   return e;
 }
 
-StageTimer::StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch)
+StageTimer::StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch,
+                       bool enabled)
     : p(const_cast<lamino_plan_s*>(plan)), s(stream), stage(stage_id), launches(nlaunch),
       start(nullptr) {
-  if (!p->profiling) return;
+  if (!p->profiling || !enabled) return;
   start = take_event(p);
   if (start) (void)hipEventRecord(start, s);
 }
@@ -412,26 +500,46 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   }
   p->tile = 0;
   p->z_chunk = o.z_chunk ? std::min(o.z_chunk, p->nz) : p->nz;
+  const size_t ncol = (size_t)p->n * p->n;
   const size_t slab_bytes = (size_t)p->grid * p->grid * 8;
   const size_t w1_bytes = (size_t)p->n_slab * p->w * 8;
-  p->slab_chunk = o.slab_chunk ? std::min(o.slab_chunk, p->n_slab)
-                               : (int)std::max<size_t>(1, std::min<size_t>(p->n_slab, kChunkTarget / slab_bytes));
-  p->theta_chunk = o.theta_chunk ? std::min(o.theta_chunk, p->n_theta)
-                                 : (int)std::max<size_t>(1, std::min<size_t>(p->n_theta, kChunkTarget / w1_bytes));
+  const int slab_auto = (int)std::max<size_t>(1, std::min<size_t>(p->n_slab, kChunkTarget / slab_bytes));
+  const int theta_auto = (int)std::max<size_t>(1, std::min<size_t>(p->n_theta, kChunkTarget / w1_bytes));
+  // host-output slices per chunk and x3 columns per chunk of spilled slab planes
+  p->io_z = o.z_chunk ? p->z_chunk
+                      : (int)std::max<size_t>(1, std::min<size_t>(p->nz, kChunkTarget / (ncol * 4)));
+  const size_t sb = lam::storage_bytes(o.storage_dtype);
+  const int col_auto = (int)std::max<size_t>(
+      256, std::min<size_t>((ncol + 255) / 256 * 256, kChunkTarget / (p->n_slab * sb) / 256 * 256));
+  p->spill_D = p->spill_g = false;
+  p->h_spill = nullptr;
+  p->s_in = p->s_out = nullptr;
+  p->pipe_ready = false;
+  for (auto& e : p->ev) e = nullptr;
+  auto reset_chunks = [&]() {
+    p->slab_chunk = o.slab_chunk ? std::min(o.slab_chunk, p->n_slab) : slab_auto;
+    p->theta_chunk = o.theta_chunk ? std::min(o.theta_chunk, p->n_theta) : theta_auto;
+    p->col_chunk = col_auto;
+  };
+  reset_chunks();
   layout_work(p);
   if (o.hbm_budget) {
-    // shrink the chunked intermediates until the workspace fits
-    while (p->work_bytes > o.hbm_budget && (p->slab_chunk > 1 || p->theta_chunk > 1)) {
-      if (p->bytes_G >= p->bytes_w1 && p->slab_chunk > 1) p->slab_chunk = (p->slab_chunk + 1) / 2;
-      else if (p->theta_chunk > 1) p->theta_chunk = (p->theta_chunk + 1) / 2;
-      else p->slab_chunk = (p->slab_chunk + 1) / 2;
-      layout_work(p);
+    // shrink the chunked intermediates until the workspace fits; failing
+    // that, keep the slab planes g, then also the spectra D, in host memory
+    bool fits = shrink_to_budget(p, o.hbm_budget);
+    for (int mode = 1; mode <= 2 && !fits; ++mode) {
+      p->spill_g = true;
+      p->spill_D = mode == 2;
+      reset_chunks();
+      fits = shrink_to_budget(p, o.hbm_budget);
     }
-    if (p->work_bytes > o.hbm_budget) {
+    if (!fits) {
       const size_t need = p->work_bytes;
       delete p;
-      return fail(LAMINO_E_BUDGET, "lamino_plan: workspace %zu bytes exceeds budget %zu", need,
-                  o.hbm_budget);
+      return fail(LAMINO_E_BUDGET,
+                  "lamino_plan: workspace %zu bytes exceeds budget %zu even with the spectra and "
+                  "slab planes in host memory",
+                  need, o.hbm_budget);
     }
   }
   build_tables(p);
@@ -472,6 +580,30 @@ int lamino_plan_info(const lamino_plan_t* p, lamino_info* info) {
   info->off_slabs = p->off_g;
   info->spectra_scale = p->spectra_scale;
   info->bytes_slabs = p->bytes_g;
+  info->spill_spectra = p->spill_D;
+  info->spill_slabs = p->spill_g;
+  info->col_chunk = p->col_chunk;
+  info->io_z = p->io_z;
+  info->host_bytes = p->host_bytes;
+  info->io_bytes = p->io_bytes;
+  return LAMINO_OK;
+}
+
+int lamino_plan_host_sizes(const lamino_plan_t* p, size_t* host_bytes, size_t* io_bytes) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_host_sizes: NULL plan");
+  if (host_bytes) *host_bytes = p->host_bytes;
+  if (io_bytes) *io_bytes = p->io_bytes;
+  return LAMINO_OK;
+}
+
+int lamino_plan_bind_host(lamino_plan_t* p, void* h_spill) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_bind_host: NULL plan");
+  if (p->host_bytes && !h_spill)
+    return fail(LAMINO_E_INVALID, "lamino_plan_bind_host: the plan needs %zu bytes of host memory",
+                p->host_bytes);
+  if ((uintptr_t)h_spill & 255)
+    return fail(LAMINO_E_INVALID, "lamino_plan_bind_host: buffer must be 256-byte aligned");
+  p->h_spill = h_spill;
   return LAMINO_OK;
 }
 
@@ -493,11 +625,57 @@ int lamino_plan_bind(lamino_plan_t* p, void* d_tables, void* d_work, void* strea
   return LAMINO_OK;
 }
 
+int lamino_plan_table_image(const lamino_plan_t* p, void* host_dst, size_t bytes) {
+  if (!p || !host_dst) return fail(LAMINO_E_INVALID, "lamino_plan_table_image: NULL argument");
+  if (bytes < p->table_bytes)
+    return fail(LAMINO_E_INVALID, "lamino_plan_table_image: %zu bytes given, %zu needed", bytes,
+                p->table_bytes);
+  std::memcpy(host_dst, p->host_tables.data(), p->table_bytes);
+  return LAMINO_OK;
+}
+
+int lamino_plan_attach(lamino_plan_t* p, void* d_tables, void* d_work) {
+  if (!p) return fail(LAMINO_E_INVALID, "lamino_plan_attach: NULL plan");
+  if (!d_tables || !d_work) return fail(LAMINO_E_INVALID, "lamino_plan_attach: NULL buffer");
+  if (((uintptr_t)d_tables & 255) || ((uintptr_t)d_work & 255))
+    return fail(LAMINO_E_INVALID, "lamino_plan_attach: buffers must be 256-byte aligned");
+  p->d_tables = d_tables;
+  p->d_work = d_work;
+  p->bound = true;
+  return LAMINO_OK;
+}
+
 static int check_call(const lamino_plan_t* p, const void* a, const void* b, const char* who) {
   if (!p) return fail(LAMINO_E_INVALID, "%s: NULL plan", who);
   if (!p->bound) return fail(LAMINO_E_UNBOUND, "%s: plan is not bound", who);
   if (!a || !b) return fail(LAMINO_E_INVALID, "%s: NULL data or volume pointer", who);
+  if (p->host_bytes && !p->h_spill)
+    return fail(LAMINO_E_UNBOUND, "%s: the plan keeps intermediates in host memory and no host "
+                "buffer is bound (lamino_plan_bind_host)", who);
   return LAMINO_OK;
+}
+
+// Operations that need the spectra and slab planes on the device.
+static int check_resident(const lamino_plan_t* p, const char* who) {
+  if (p->spill_D || p->spill_g)
+    return fail(LAMINO_E_UNSUPPORTED, "%s: not available for a plan whose intermediates live in "
+                "host memory (raise opts.hbm_budget)", who);
+  return LAMINO_OK;
+}
+
+int lamino_fbp_host(const lamino_plan_t* p, const void* h_data, float* h_vol, void* d_io,
+                    void* stream) {
+  const int c = check_call(p, h_data, h_vol, "lamino_fbp_host");
+  if (c) return c;
+  if (!d_io) return fail(LAMINO_E_INVALID, "lamino_fbp_host: NULL staging buffer");
+  if ((uintptr_t)d_io & 255)
+    return fail(LAMINO_E_INVALID, "lamino_fbp_host: staging buffer must be 256-byte aligned");
+  lam::BackprojOpts o;
+  o.h_data = h_data;
+  o.h_vol = h_vol;
+  o.io = d_io;
+  hipError_t e = lam::run_backprojection(p, nullptr, nullptr, true, static_cast<hipStream_t>(stream), o);
+  return e == hipSuccess ? LAMINO_OK : hip_fail(e, "lamino_fbp_host");
 }
 
 int lamino_fbp(const lamino_plan_t* p, const void* d_data, float* d_vol, void* stream) {
@@ -549,7 +727,9 @@ int lamino_adj(const lamino_plan_t* p, const void* d_data, float* d_vol, void* s
 }
 
 int lamino_fwd(const lamino_plan_t* p, const float* d_vol, void* d_data, void* stream) {
-  const int c = check_call(p, d_vol, d_data, "lamino_fwd");
+  int c = check_call(p, d_vol, d_data, "lamino_fwd");
+  if (c) return c;
+  c = check_resident(p, "lamino_fwd");
   if (c) return c;
   if (lam::integer_dtype(p->opts.data_dtype))
     return fail(LAMINO_E_INVALID, "lamino_fwd: integer data is accepted as input only");
@@ -638,7 +818,9 @@ int lamino_admm_tv_state_bytes(const lamino_plan_t* p, size_t* bytes) {
 
 int lamino_admm_tv(const lamino_plan_t* p, const float* d_data, float* d_vol, double alpha,
                    double rho, int outer, int inner, int resume, void* d_state, void* stream) {
-  const int c = check_call(p, d_data, d_vol, "lamino_admm_tv");
+  int c = check_call(p, d_data, d_vol, "lamino_admm_tv");
+  if (c) return c;
+  c = check_resident(p, "lamino_admm_tv");
   if (c) return c;
   if (!d_state) return fail(LAMINO_E_INVALID, "lamino_admm_tv: NULL state");
   if ((uintptr_t)d_state & 255)
@@ -658,6 +840,10 @@ int lamino_admm_tv(const lamino_plan_t* p, const float* d_data, float* d_vol, do
 
 int lamino_plan_destroy(lamino_plan_t* p) {
   if (!p) return LAMINO_OK;
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (p->s_in) (void)hipStreamDestroy(p->s_in);
+  if (p->s_out) (void)hipStreamDestroy(p->s_out);
   for (auto& m : p->marks) {
     (void)hipEventSynchronize(m.stop);
     (void)hipEventDestroy(m.start);

@@ -74,6 +74,28 @@ struct lamino_plan_s {
   size_t off_w1, off_D, off_G, off_g, off_phase, off_dyn;
   size_t bytes_w1, bytes_D, bytes_G, bytes_g;
   size_t work_bytes;
+  // Out-of-core layout: when the resident workspace exceeds opts.hbm_budget
+  // the spectra D and / or the slab planes g live in a caller-owned host
+  // buffer (host_bytes; D at off_hD, g at off_hg) and the device workspace
+  // holds double-buffered chunks instead: D[l][theta chunk][k] written by the
+  // detector stage (off_Dout), D[slab chunk][theta][k] read by gridding
+  // (off_Din), g[slab chunk][y][x] written by the slab stage (off_gout) and
+  // g[l][column chunk] read by the x3 transform (off_gcol, col_chunk columns).
+  bool spill_D, spill_g;
+  int col_chunk;
+  size_t off_Dout[2], off_Din[2], off_gout[2], off_gcol[2];
+  size_t host_bytes, off_hD, off_hg;
+  void* h_spill;
+  // host-memory input / output (lamino_fbp_host): device staging buffer of
+  // io_bytes with data chunks [theta_chunk][h][w] at off_in[] and volume
+  // chunks at off_vout[] (io_z slices, or all slices of col_chunk columns
+  // when g is spilled)
+  int io_z;
+  size_t off_in[2], off_vout[2], io_bytes;
+  // streams and events of the out-of-core pipeline (created on first use)
+  hipStream_t s_in, s_out;
+  hipEvent_t ev[16];
+  bool pipe_ready;
   std::vector<unsigned char> host_tables;
   void* d_tables;
   void* d_work;
@@ -93,7 +115,12 @@ struct lamino_plan_s {
 
 namespace lam {
 
-KParams make_params(const lamino_plan_s* p, bool fbp_filter);
+// Kernel parameters with the table and workspace pointers of the plan's
+// bound buffers, or of the buffers given (tables / work not NULL).
+KParams make_params(const lamino_plan_s* p, bool fbp_filter, const void* tables = nullptr,
+                    void* work = nullptr);
+// Records a thread-local error message (lamino_last_error) and returns code.
+int api_fail(int code, const char* fmt, ...);
 size_t storage_bytes(int dtype);  // bytes of one stored complex value
 size_t data_bytes(int dtype);     // bytes of one real data value
 bool integer_dtype(int dtype);    // U8 / U16: input-only data types
@@ -104,7 +131,8 @@ struct StageTimer {
   hipStream_t s;
   int stage, launches;
   hipEvent_t start;
-  StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch);
+  StageTimer(const lamino_plan_s* plan, hipStream_t stream, int stage_id, int nlaunch,
+             bool enabled = true);
   ~StageTimer();
 };
 
@@ -113,6 +141,8 @@ struct StageTimer {
 // a rotation-axis offset (detector columns; applied as a phase ramp on the
 // row spectra) and the output slices [z_first, z_first + z_count) written
 // to d_vol[0 .. z_count).
+// Device buffers other than the plan's bound ones (tables / work not NULL,
+// same layouts), and stage timing off (timing = false: no events created).
 struct BackprojOpts {
   const float* dark = nullptr;
   const float* flat = nullptr;
@@ -120,9 +150,19 @@ struct BackprojOpts {
   double center_shift = 0.0;
   int z_first = 0;
   int z_count = -1;  // -1: all nz slices
+  const void* tables = nullptr;
+  void* work = nullptr;
+  bool timing = true;
+  // host-memory input and output streamed through the staging buffer io
+  // (lamino_fbp_host); d_data / d_vol are then NULL
+  const void* h_data = nullptr;
+  float* h_vol = nullptr;
+  void* io = nullptr;
 };
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
                               bool fbp_filter, hipStream_t s, const BackprojOpts& o = BackprojOpts());
+// Creates the pipeline streams and events of a plan (no-op after the first call).
+hipError_t ensure_pipe(lamino_plan_s* p);
 hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        hipStream_t s);
 

@@ -37,9 +37,10 @@ constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 // Column pairs (c, c+1) of projection theta0 + blockIdx.y packed as one
 // complex h_p-point FFT along v; the two real spectra are separated by
 // Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
+// data holds projections data_th0 .. (a whole input or a streamed chunk).
 __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
-                                                      int cp) {
+                                                      int cp, int data_th0) {
   __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   const int wide = 2 * cp;
   const float iwide = 1.f / (float)wide;
   float* bf = reinterpret_cast<float*>(buf);
-  const size_t row0 = (size_t)th * p.h;
+  const size_t row0 = (size_t)(th - data_th0) * p.h;
   const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
   stage_in<float>(
       p.h * wide,
@@ -86,11 +87,12 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 }
 
 // Rows l of the column spectra: w_p-point FFT along u, times the transfer
-// function, stored as D[l][theta][k] (k = m mod w_p).
+// function, stored as D[l][theta - d_th0][k] (k = m mod w_p) with d_nth
+// projections per slab (all of them, or one streamed chunk).
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
                                                       const float2* __restrict__ phase, int theta0,
-                                                      int rows) {
+                                                      int rows, int d_nth, int d_th0) {
   __shared__ float2 buf[LDS_CPLX];
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
@@ -116,7 +118,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
     if (l < p.n_slab) {
       float2 v = cscale(res[e], filt[k]);
       if (phase) v = cmul(v, phase[k]);
-      st_c(D, ((size_t)l * p.n_theta + th) * wp + k, v, p.storage_dtype);
+      st_c(D, ((size_t)l * d_nth + (th - d_th0)) * wp + k, v, p.storage_dtype);
     }
   }
 }
@@ -329,7 +331,7 @@ struct SpreadCand {
 // PREC 0: bf16 x3 (float32 storage), 1: float16 x1, 2: bfloat16 x1
 template <int M, int PREC>
 __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
-                                               float2* __restrict__ G, int slab0) {
+                                               float2* __restrict__ G, int slab0, int d_l0) {
   constexpr int W = 2 * M;
   constexpr int WS = W + 2;  // slot: zero, W taps, zero
   // row weight: bf16 hi | lo (PREC 0) or one 16-bit value; column value:
@@ -426,7 +428,8 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
           cd.ly = (int)floorf(cd.Y) - M + 1 - oy;
           cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
           if (cd.use)
-            cd.c = ld_c(D, ((size_t)l * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)), p.storage_dtype);
+            cd.c = ld_c(D, ((size_t)(l - d_l0) * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)),
+                        p.storage_dtype);
         };
         SpreadCand cur;
         fetch(0, cur);
@@ -655,8 +658,10 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
   }
 }
 
+// g holds slabs g_l0 .. (all of them, or one streamed chunk).
 __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
-                                                      void* __restrict__ g, int slab0, int cols) {
+                                                      void* __restrict__ g, int slab0, int cols,
+                                                      int g_l0) {
   __shared__ float2 buf[LDS_CPLX];
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
@@ -681,7 +686,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
     const int ix = ix0 + c;
     if (ix >= p.n) continue;
     const float2 v = cscale(res[c * N + ((y - p.n / 2) & (N - 1))], p.deapod[ix] * p.deapod[y]);
-    st_c(g, ((size_t)l * p.n + y) * p.n + ix, v, p.storage_dtype);
+    st_c(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix, v, p.storage_dtype);
   }
 }
 
@@ -809,15 +814,16 @@ __device__ __forceinline__ void x3_adj_loadb(const KParams& p, const void* g, in
   }
 }
 
-// vol[z0 + z][col] for z in [0, nzc).  The operands of K-step k0 + 16 are
-// loaded while the products of step k0 run.
+// vol[z0 - out_z0 + z][col0 + col] for z in [0, nzc) and the ncol columns
+// col of g (slab stride g_ld columns); vol rows have v_ld columns.  The
+// operands of K-step k0 + 16 are loaded while the products of step k0 run.
 template <int PREC>
 __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void* __restrict__ g,
-                                                          float* __restrict__ vol, int z0,
+                                                          int g_ld, float* __restrict__ vol,
+                                                          int v_ld, int col0, int ncol, int z0,
                                                           int nzc, int out_z0) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
-  const int ncol = p.n * p.n;
   const int col = blockIdx.x * 32 + r;
   const int zt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;
   if (zt >= nzc) return;
@@ -831,12 +837,12 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
   v16f acc[X3_ZT] = {};
   X3AdjB<PREC> bc, bn;
   v8u ahc[X3_ZT], alc[X3_ZT], ahn[X3_ZT], aln[X3_ZT];
-  x3_adj_loadb<PREC>(p, g, ncol, cok, cidx, 0, h, bc);
+  x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, 0, h, bc);
 #pragma unroll
   for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, 0, ahc[i], alc[i]);
   for (int k0 = 0; k0 < K; k0 += 16) {
     const int kn = min(k0 + 16, K - 16);  // the last step reloads itself
-    x3_adj_loadb<PREC>(p, g, ncol, cok, cidx, kn, h, bn);
+    x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, kn, h, bn);
 #pragma unroll
     for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, kn >> 4, ahn[i], aln[i]);
     v8u bh, bl;
@@ -871,7 +877,7 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * ncol + col] = acc[i][v] * outs;
+      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * v_ld + col0 + col] = acc[i][v] * outs;
     }
 }
 
@@ -959,8 +965,10 @@ __device__ __forceinline__ float absmax16(uint4 v) {
 // 16-byte loads (four in flight per thread) when the input is 16-byte
 // aligned, element loads for the rest
 template <int DT>
+// accumulate != 0: each block keeps the larger of its new maximum and the
+// value already in part[blockIdx.x] (inputs scanned chunk by chunk)
 __global__ __launch_bounds__(256) void k_absmax_partial(const void* __restrict__ x, size_t n,
-                                                         float* __restrict__ part) {
+                                                         float* __restrict__ part, int accumulate) {
   constexpr size_t PER = DT == LAMINO_F32 ? 4 : (DT == LAMINO_U8 ? 16 : 8);  // elements per chunk
   __shared__ float red[4];
   float m = 0.f;
@@ -982,7 +990,10 @@ __global__ __launch_bounds__(256) void k_absmax_partial(const void* __restrict__
   for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  if (threadIdx.x == 0) {
+    const float mb = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    part[blockIdx.x] = accumulate ? fmaxf(mb, part[blockIdx.x]) : mb;
+  }
 }
 
 // nb partial maxima (0: none) and a host-known bound `extra`
@@ -1008,35 +1019,46 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // Sets the float16 input factor of a call from its input (x != NULL) or from
 // a known bound alone.
+// Block maxima of x[0 .. n) into dyn[2 ..] (nb blocks); with accumulate the
+// maxima of earlier chunks are kept (nb must then be the same for every chunk).
+static void absmax_partial(const KParams& kp, const void* x, size_t n, int dt, int nb,
+                           int accumulate, hipStream_t s) {
+  float* part = const_cast<float*>(kp.dyn) + 2;
+  switch (dt) {
+    case LAMINO_F32: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F32>, dim3(nb), dim3(256), 0, s, x, n, part, accumulate); break;
+    case LAMINO_F16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F16>, dim3(nb), dim3(256), 0, s, x, n, part, accumulate); break;
+    case LAMINO_BF16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_BF16>, dim3(nb), dim3(256), 0, s, x, n, part, accumulate); break;
+    case LAMINO_U8: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U8>, dim3(nb), dim3(256), 0, s, x, n, part, accumulate); break;
+    default: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U16>, dim3(nb), dim3(256), 0, s, x, n, part, accumulate); break;
+  }
+}
+
+// Sets the float16 input factor of a call from its input (x != NULL) or from
+// a known bound alone.
 static void input_factor(const KParams& kp, const void* x, size_t n, int dt, float bound,
                          hipStream_t s) {
   float* dyn = const_cast<float*>(kp.dyn);
   int nb = 0;
   if (x) {
     nb = (int)std::min<size_t>(ABSMAX_BLOCKS, std::max<size_t>(1, (n + 255) / 256));
-    switch (dt) {
-      case LAMINO_F32: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F32>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
-      case LAMINO_F16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_F16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
-      case LAMINO_BF16: hipLaunchKernelGGL(k_absmax_partial<LAMINO_BF16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
-      case LAMINO_U8: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U8>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
-      default: hipLaunchKernelGGL(k_absmax_partial<LAMINO_U16>, dim3(nb), dim3(256), 0, s, x, n, dyn + 2); break;
-    }
+    absmax_partial(kp, x, n, dt, nb, 0, s);
   }
   hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, dyn, nb, bound);
 }
 
 static int spread_tile(const KParams& p) { return p.grid <= 128 ? (p.grid < 32 ? p.grid : 32) : 64; }
 
+// D holds slabs d_l0 .. (all of them, or one streamed chunk)
 template <int M>
-static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns,
+static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns, int d_l0,
                           hipStream_t s) {
   const int tiles = (kp.grid / SP_T) * (kp.grid / SP_T);
   if (kp.storage_dtype == LAMINO_F32)
-    hipLaunchKernelGGL((k_spread<M, 0>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 0>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
   else if (kp.storage_dtype == LAMINO_F16)
-    hipLaunchKernelGGL((k_spread<M, 1>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 1>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
   else
-    hipLaunchKernelGGL((k_spread<M, 2>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0);
+    hipLaunchKernelGGL((k_spread<M, 2>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
 }
 template <int M>
 static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, int ns, int tile,
@@ -1045,16 +1067,16 @@ static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, i
   hipLaunchKernelGGL(k_interp<M>, dim3(ns, tiles), dim3(NT), 0, s, kp, G, D, s0, tile);
 }
 
-static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns,
+static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns, int d_l0,
                             hipStream_t s) {
   switch (kp.M) {
-    case 2: launch_spread<2>(kp, D, G, s0, ns, s); break;
-    case 3: launch_spread<3>(kp, D, G, s0, ns, s); break;
-    case 4: launch_spread<4>(kp, D, G, s0, ns, s); break;
-    case 5: launch_spread<5>(kp, D, G, s0, ns, s); break;
-    case 6: launch_spread<6>(kp, D, G, s0, ns, s); break;
-    case 7: launch_spread<7>(kp, D, G, s0, ns, s); break;
-    default: launch_spread<8>(kp, D, G, s0, ns, s); break;
+    case 2: launch_spread<2>(kp, D, G, s0, ns, d_l0, s); break;
+    case 3: launch_spread<3>(kp, D, G, s0, ns, d_l0, s); break;
+    case 4: launch_spread<4>(kp, D, G, s0, ns, d_l0, s); break;
+    case 5: launch_spread<5>(kp, D, G, s0, ns, d_l0, s); break;
+    case 6: launch_spread<6>(kp, D, G, s0, ns, d_l0, s); break;
+    case 7: launch_spread<7>(kp, D, G, s0, ns, d_l0, s); break;
+    default: launch_spread<8>(kp, D, G, s0, ns, d_l0, s); break;
   }
 }
 static void interp_dispatch(const KParams& kp, const float2* G, void* D, int s0, int ns,
@@ -1075,63 +1097,263 @@ static inline char* wptr(const lamino_plan_s* p, size_t off) {
   return static_cast<char*>(p->d_work) + off;
 }
 
+// x3 transform of the columns [col0, col0 + ncol) of the slabs in g (slab
+// stride g_ld columns): vol[z - out_z0][vcol0 + col] for z in [z0, z0 + nzc),
+// vol rows of v_ld columns.
+static void launch_x3_adj(const KParams& kp, const void* g, int g_ld, float* vol, int v_ld,
+                          int vcol0, int ncol, int z0, int nzc, int out_z0, hipStream_t s) {
+  const dim3 grid(cdiv(ncol, 32), cdiv(nzc, X3_ROWS));
+  if (kp.storage_dtype == LAMINO_F32)
+    hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+  else if (kp.storage_dtype == LAMINO_F16)
+    hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+  else
+    hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+}
+
+// Backprojection pipeline.  Device-resident plans with device data and
+// volume run every stage on `s` in order.  Otherwise (host data or volume,
+// spectra or slab planes in host memory) the chunks move between host and
+// device on the plan's copy streams: s_in brings chunks in, s_out takes
+// results out, each through two alternating buffers, and events order
+//   copy-in of chunk c  after  the kernels of chunk c - 2 released its buffer,
+//   kernels of chunk c  after  its copy-in and after the copy-out of chunk
+//                              c - 2 released the output buffer,
+//   copy-out of chunk c after  the kernels of chunk c.
+// Events 0-1: copy-in done, 2-3: input buffer released, 4-5: kernels done,
+// 6-7: copy-out done (index = chunk parity); 8-9: stream joins.
 hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float* d_vol,
                               bool fbp_filter, hipStream_t s, const BackprojOpts& o) {
-  KParams kp = make_params(p, fbp_filter);
+  KParams kp = make_params(p, fbp_filter, o.tables, o.work);
+  char* const work = static_cast<char*>(o.work ? o.work : p->d_work);
+  char* const io = static_cast<char*>(o.io);
+  char* const hsp = static_cast<char*>(p->h_spill);
+  const bool timing = o.timing;
+  const bool host_in = o.h_data != nullptr, host_out = o.h_vol != nullptr;
+  const bool piped = host_in || host_out || p->spill_D || p->spill_g;
+  lamino_plan_s* pm = const_cast<lamino_plan_s*>(p);
+  hipStream_t si = nullptr, so = nullptr;
+  hipEvent_t* ev = pm->ev;
+  if (piped) {
+    const hipError_t e = ensure_pipe(pm);
+    if (e != hipSuccess) return e;
+    si = p->s_in;
+    so = p->s_out;
+    // every event starts complete at this point of s, and the copy streams
+    // start after the work already on s
+    for (int i = 0; i < 10; ++i) (void)hipEventRecord(ev[i], s);
+    (void)hipStreamWaitEvent(si, ev[8], 0);
+    (void)hipStreamWaitEvent(so, ev[8], 0);
+  }
+  auto rec = [&](int i, hipStream_t st) { (void)hipEventRecord(ev[i], st); };
+  auto wait = [&](hipStream_t st, int i) { (void)hipStreamWaitEvent(st, ev[i], 0); };
+  const size_t sb = storage_bytes(p->opts.storage_dtype);
+  const size_t db = data_bytes(p->opts.data_dtype);
+  const size_t ncol = (size_t)p->n * p->n;
+  const size_t proj = (size_t)p->h * p->w;  // elements per projection
   kp.dark = o.dark;
   kp.flat = o.flat;
   kp.min_ratio = o.min_ratio;
   if (kp.dyn) {
-    // raw counts: the corrected values are bounded by -log(min_ratio)
-    if (o.dark) input_factor(kp, nullptr, 0, 0, -std::log(o.min_ratio), s);
-    else input_factor(kp, d_data, (size_t)p->n_theta * p->h * p->w, p->opts.data_dtype, 0.f, s);
+    if (o.dark) {
+      // raw counts: the corrected values are bounded by -log(min_ratio)
+      input_factor(kp, nullptr, 0, 0, -std::log(o.min_ratio), s);
+    } else if (!host_in) {
+      input_factor(kp, d_data, (size_t)p->n_theta * proj, p->opts.data_dtype, 0.f, s);
+    } else {
+      // host data: one scan pass over the projection chunks, maxima kept per block
+      for (int t0 = 0, c = 0; t0 < p->n_theta; t0 += p->theta_chunk, ++c) {
+        const int nt = std::min(p->theta_chunk, p->n_theta - t0);
+        char* buf = io + p->off_in[c & 1];
+        wait(si, 2 + (c & 1));
+        (void)hipMemcpyAsync(buf, static_cast<const char*>(o.h_data) + (size_t)t0 * proj * db,
+                             (size_t)nt * proj * db, hipMemcpyHostToDevice, si);
+        rec(c & 1, si);
+        wait(s, c & 1);
+        absmax_partial(kp, buf, (size_t)nt * proj, p->opts.data_dtype, ABSMAX_BLOCKS, c > 0, s);
+        rec(2 + (c & 1), s);
+      }
+      hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(256), 0, s, const_cast<float*>(kp.dyn),
+                         ABSMAX_BLOCKS, 0.f);
+    }
   }
   float2* phase = nullptr;
   if (o.center_shift != 0.0) {
-    phase = reinterpret_cast<float2*>(wptr(p, p->off_phase));
+    phase = reinterpret_cast<float2*>(work + p->off_phase);
     hipLaunchKernelGGL(k_axis_phase, dim3(cdiv(p->w_p, 256)), dim3(256), 0, s, phase, p->w_p,
                        o.center_shift);
   }
-  float2* W1 = reinterpret_cast<float2*>(wptr(p, p->off_w1));
-  void* D = wptr(p, p->off_D);
-  float2* G = reinterpret_cast<float2*>(wptr(p, p->off_G));
-  void* g = wptr(p, p->off_g);
+  float2* W1 = reinterpret_cast<float2*>(work + p->off_w1);
+  void* D = work + p->off_D;
+  float2* G = reinterpret_cast<float2*>(work + p->off_G);
+  void* g = work + p->off_g;
+  char* hD = hsp + p->off_hD;
+  char* hg = hsp + p->off_hg;
+
+  // ---- detector stage: per projection chunk
   const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
   const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
-  for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
+  for (int t0 = 0, c = 0; t0 < p->n_theta; t0 += p->theta_chunk, ++c) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
-    StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
-    hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp, d_data,
-                       W1, t0, cp);
-    hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
-                       (const float2*)W1, D, kp.filt, (const float2*)phase, t0, rows_w);
+    const void* src = d_data;
+    int src_th0 = 0;
+    if (host_in) {
+      char* buf = io + p->off_in[c & 1];
+      wait(si, 2 + (c & 1));
+      (void)hipMemcpyAsync(buf, static_cast<const char*>(o.h_data) + (size_t)t0 * proj * db,
+                           (size_t)nt * proj * db, hipMemcpyHostToDevice, si);
+      rec(c & 1, si);
+      wait(s, c & 1);
+      src = buf;
+      src_th0 = t0;
+    }
+    void* Dt = D;
+    int d_nth = p->n_theta, d_th0 = 0;
+    if (p->spill_D) {
+      Dt = work + p->off_Dout[c & 1];
+      d_nth = p->theta_chunk;
+      d_th0 = t0;
+      wait(s, 6 + (c & 1));
+    }
+    {
+      StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2, timing);
+      hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp, src,
+                         W1, t0, cp, src_th0);
+      if (host_in) rec(2 + (c & 1), s);
+      hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
+                         (const float2*)W1, Dt, kp.filt, (const float2*)phase, t0, rows_w, d_nth,
+                         d_th0);
+    }
+    if (p->spill_D) {
+      // D[l][t0 .. t0 + nt)[k] of every slab l into the host spectra
+      rec(4 + (c & 1), s);
+      wait(so, 4 + (c & 1));
+      const size_t wrow = (size_t)p->w_p * sb;
+      (void)hipMemcpy2DAsync(hD + (size_t)t0 * wrow, (size_t)p->n_theta * wrow, Dt,
+                             (size_t)p->theta_chunk * wrow, (size_t)nt * wrow, p->n_slab,
+                             hipMemcpyDeviceToHost, so);
+      rec(6 + (c & 1), so);
+    }
   }
+  if (p->spill_D) {
+    // the host spectra are complete before any slab chunk is read back
+    rec(9, so);
+    wait(si, 9);
+  }
+
+  // ---- gridding and slab stages: per slab chunk
   const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
   const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
-  for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
+  for (int s0 = 0, j = 0; s0 < p->n_slab; s0 += p->slab_chunk, ++j) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
-    {
-      StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
-      spread_dispatch(kp, D, G, s0, ns, s);
+    const void* Dg = D;
+    int d_l0 = 0;
+    if (p->spill_D) {
+      char* buf = work + p->off_Din[j & 1];
+      const size_t slab = (size_t)p->n_theta * p->w_p * sb;
+      wait(si, 2 + (j & 1));
+      (void)hipMemcpyAsync(buf, hD + (size_t)s0 * slab, (size_t)ns * slab, hipMemcpyHostToDevice, si);
+      rec(j & 1, si);
+      wait(s, j & 1);
+      Dg = buf;
+      d_l0 = s0;
     }
-    StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
-    hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp, G,
-                       rows_g);
-    hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
-                       (const float2*)G, g, s0, cols_g);
+    {
+      StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1, timing);
+      spread_dispatch(kp, Dg, G, s0, ns, d_l0, s);
+    }
+    if (p->spill_D) rec(2 + (j & 1), s);
+    void* gt = g;
+    int g_l0 = 0;
+    if (p->spill_g) {
+      gt = work + p->off_gout[j & 1];
+      g_l0 = s0;
+      wait(s, 6 + (j & 1));
+    }
+    {
+      StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2, timing);
+      hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp, G,
+                         rows_g);
+      hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
+                         (const float2*)G, gt, s0, cols_g, g_l0);
+    }
+    if (p->spill_g) {
+      rec(4 + (j & 1), s);
+      wait(so, 4 + (j & 1));
+      (void)hipMemcpyAsync(hg + (size_t)s0 * ncol * sb, gt, (size_t)ns * ncol * sb,
+                           hipMemcpyDeviceToHost, so);
+      rec(6 + (j & 1), so);
+    }
   }
-  const int ncol = p->n * p->n;
+
+  // ---- x3 transform
   const int zb = o.z_first, ze = o.z_count < 0 ? p->nz : o.z_first + o.z_count;
-  for (int z0 = zb; z0 < ze; z0 += p->z_chunk) {
-    const int nzc = std::min(p->z_chunk, ze - z0);
-    StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
-    const dim3 grid(cdiv(ncol, 32), cdiv(nzc, X3_ROWS));
-    if (kp.storage_dtype == LAMINO_F32)
-      hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
-    else if (kp.storage_dtype == LAMINO_F16)
-      hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
-    else
-      hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, (const void*)g, d_vol, z0, nzc, zb);
+  if (!p->spill_g) {
+    // z chunks (host output: io_z slices per chunk through the staging buffer)
+    const int zc = host_out ? p->io_z : p->z_chunk;
+    for (int z0 = zb, k = 0; z0 < ze; z0 += zc, ++k) {
+      const int nzc = std::min(zc, ze - z0);
+      float* out = d_vol;
+      int out_z0 = zb;
+      if (host_out) {
+        out = reinterpret_cast<float*>(io + p->off_vout[k & 1]);
+        out_z0 = z0;
+        wait(s, 6 + (k & 1));
+      }
+      {
+        StageTimer timer(p, s, LAMINO_STAGE_X3, 1, timing);
+        launch_x3_adj(kp, g, (int)ncol, out, (int)ncol, 0, (int)ncol, z0, nzc, out_z0, s);
+      }
+      if (host_out) {
+        rec(4 + (k & 1), s);
+        wait(so, 4 + (k & 1));
+        (void)hipMemcpyAsync(o.h_vol + (size_t)(z0 - zb) * ncol, out, (size_t)nzc * ncol * 4,
+                             hipMemcpyDeviceToHost, so);
+        rec(6 + (k & 1), so);
+      }
+    }
+  } else {
+    // column chunks of all slices; the host slab planes are complete first
+    rec(9, so);
+    wait(si, 9);
+    const int cc = p->col_chunk;
+    const int nzo = ze - zb;
+    for (int c0 = 0, k = 0; c0 < (int)ncol; c0 += cc, ++k) {
+      const int ncc = std::min(cc, (int)ncol - c0);
+      char* buf = work + p->off_gcol[k & 1];
+      wait(si, 2 + (k & 1));
+      (void)hipMemcpy2DAsync(buf, (size_t)cc * sb, hg + (size_t)c0 * sb, ncol * sb, (size_t)ncc * sb,
+                             p->n_slab, hipMemcpyHostToDevice, si);
+      rec(k & 1, si);
+      wait(s, k & 1);
+      float* out = d_vol;
+      int v_ld = (int)ncol, vcol0 = c0;
+      if (host_out) {
+        out = reinterpret_cast<float*>(io + p->off_vout[k & 1]);
+        v_ld = cc;
+        vcol0 = 0;
+        wait(s, 6 + (k & 1));
+      }
+      {
+        StageTimer timer(p, s, LAMINO_STAGE_X3, 1, timing);
+        launch_x3_adj(kp, buf, cc, out, v_ld, vcol0, ncc, zb, nzo, zb, s);
+      }
+      rec(2 + (k & 1), s);
+      if (host_out) {
+        rec(4 + (k & 1), s);
+        wait(so, 4 + (k & 1));
+        (void)hipMemcpy2DAsync(o.h_vol + c0, ncol * 4, out, (size_t)cc * 4, (size_t)ncc * 4, nzo,
+                               hipMemcpyDeviceToHost, so);
+        rec(6 + (k & 1), so);
+      }
+    }
+  }
+  if (piped) {
+    // the call is complete on s once both copy streams have drained
+    rec(8, si);
+    rec(9, so);
+    wait(s, 8);
+    wait(s, 9);
   }
   return hipGetLastError();
 }

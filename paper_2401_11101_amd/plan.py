@@ -71,6 +71,15 @@ class Plan:
             self.work = work
             _abi.lamino_plan_bind(self._h, ctypes.c_void_p(self.tables.data_ptr()),
                                   ctypes.c_void_p(self.work.data_ptr()), _stream_handle(stream))
+        # out-of-core plan (workspace above hbm_budget): the spectra and / or
+        # slab planes live in pinned host memory owned here
+        self.host_spill = None
+        host_bytes, _ = _abi.lamino_plan_host_sizes(self._h)
+        if host_bytes:
+            self.host_spill = torch.empty(host_bytes + 256, dtype=torch.uint8, pin_memory=True)
+            off = (-self.host_spill.data_ptr()) % 256
+            _abi.lamino_plan_bind_host(self._h, ctypes.c_void_p(self.host_spill.data_ptr() + off))
+        self._io = None
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -97,6 +106,28 @@ class Plan:
         self._check(out, self.shape_vol, torch.float32, "out")
         _abi.lamino_fbp(self._h, ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                         _stream_handle(stream))
+        return out
+
+    def fbp_host(self, data, out=None, stream=None):
+        """FBP with the data and the volume in (pinned) host memory: chunks
+        stream through a device staging buffer while the kernels run.  The
+        volume is complete when the stream has finished."""
+        if not isinstance(data, torch.Tensor) or data.device.type != "cpu":
+            raise ValueError("data must be a host tensor")
+        if tuple(data.shape) != self.shape_data or data.dtype != self.torch_data_dtype or \
+                not data.is_contiguous():
+            raise ValueError(f"data must be a contiguous {self.torch_data_dtype} host tensor of "
+                             f"shape {self.shape_data}")
+        if out is None:
+            out = torch.empty(self.shape_vol, dtype=torch.float32, pin_memory=True)
+        elif out.device.type != "cpu" or tuple(out.shape) != self.shape_vol or \
+                out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float32 host tensor of shape {self.shape_vol}")
+        if self._io is None:
+            _, io_bytes = _abi.lamino_plan_host_sizes(self._h)
+            self._io = torch.empty(max(io_bytes, 256), dtype=torch.uint8, device=self.device)
+        _abi.lamino_fbp_host(self._h, ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(self._io.data_ptr()), _stream_handle(stream))
         return out
 
     def fbp_raw(self, raw, dark, flat, min_ratio=1e-6, out=None, stream=None):

@@ -12,8 +12,13 @@ A request is admitted as soon as a slot of its class is free or a new slot
 fits in the HBM budget; its FBP is enqueued on the slot's stream at once,
 so requests that arrive while others run overlap on the device.  Geometry
 tables depend on the tilt, so each request gets its own host plan (cheap:
-double-precision tables on the host) bound to the slot's cached device
-buffers; plans of repeated (shape, tilt) pairs are cached.  Completion is
+double-precision tables on the host); its table image is copied into the
+slot's pinned staging buffer and uploaded asynchronously on the slot's
+stream, and the plan is attached to the slot's device buffers without any
+host synchronisation.  Plans of repeated (shape, tilt) pairs are cached.
+The HBM budget counts every slot's tables and workspace plus, for each
+running request, its output volume and the device copy of host data; a
+request that could never fit is refused at submission.  Completion is
 detected with an event per request; latency = completion - arrival.
 
 Every result is the same whether a request runs alone or in a mix: the
@@ -61,13 +66,19 @@ class _Slot:
         self.stream = torch.cuda.Stream(device=device)  # default priority
         self.busy = None
         self.bytes = plan.tables.numel() + plan.work.numel()
+        # pinned staging copy of a request's table image: rewritten only when
+        # the slot is free, i.e. after the previous upload from it has run
+        self.stage = torch.empty(plan.tables.numel(), dtype=torch.uint8, pin_memory=True)
 
 
 class Server:
     """Admits FBP requests into per-class slots and runs them concurrently.
 
     max_slots bounds the number of concurrently running requests;
-    hbm_budget bounds the bytes of all slot workspaces (0: no bound);
+    hbm_budget bounds the device bytes of all slots (tables and workspaces)
+    plus the outputs and device data copies of the running requests (0: no
+    bound); a request larger than the budget on its own raises ValueError at
+    submission;
     result_on_host copies every volume into pinned host memory (Request.out_host);
     keep_results=False drops a request's volumes once it has finished (a stream
     whose consumer only needs the timings keeps no outputs alive)."""
@@ -114,42 +125,57 @@ class Server:
             _abi.lamino_plan_destroy(old)
         return h
 
-    def _footprint(self, req):
-        return sum(_abi.lamino_plan_sizes(self._host_plan(req)))
+    def _slot_bytes(self, req):
+        """Device bytes of a slot for the request's class (tables + workspace)."""
+        t, w = _abi.lamino_plan_sizes(self._host_plan(req))
+        return max(t, 256) + max(w, 256)
+
+    @staticmethod
+    def _request_bytes(req):
+        """Device bytes a running request holds besides its slot: the output
+        volume and, for host data, the device copy of the data."""
+        nz, n = req.shape[0], req.shape[1]
+        b = nz * n * n * 4
+        if req.data.device.type == "cpu":
+            b += req.data.numel() * req.data.element_size()
+        return b
 
     def _used_bytes(self):
-        return sum(s.bytes for s in self.slots)
+        return sum(s.bytes + (self._request_bytes(s.busy) if s.busy is not None else 0)
+                   for s in self.slots)
 
     # ------------------------------------------------------------ admission
     def submit(self, req):
         if req.data.device.type == "cpu" and not req.data.is_pinned():
             raise ValueError(f"request {req.rid}: host data must be in pinned memory")
+        if self.hbm_budget:
+            need = self._slot_bytes(req) + self._request_bytes(req)
+            if need > self.hbm_budget:
+                raise ValueError(f"request {req.rid} needs {need} bytes of HBM, above the budget "
+                                 f"of {self.hbm_budget}")
         self.queue.append(req)
         self._admit()
 
     def _free_slot(self, req):
         key = self._class_key(req)
-        for s in self.slots:
-            if s.busy is None and s.key == key:
-                return s
-        if len(self.slots) < self.max_slots or any(s.busy is None for s in self.slots):
-            need = self._footprint(req)
-            # evict idle slots of other classes until the new one fits
-            while (self.hbm_budget and self._used_bytes() + need > self.hbm_budget) or \
-                    len(self.slots) >= self.max_slots:
-                idle = [s for s in self.slots if s.busy is None and s.key != key]
-                if not idle:
-                    return None
-                self.slots.remove(idle[0])
-            if self.hbm_budget and need > self.hbm_budget:
-                raise ValueError(f"request {req.rid} needs {need} bytes, above the HBM budget")
-            nz, n, nt, h, w = req.shape
-            proto = Plan(nz, n, nt, h, w, req.tilt, data_dtype=self.data_dtype,
-                         storage_dtype=self.storage_dtype, filter=self.filter, device=self.device)
-            slot = _Slot(key, proto, self.device)
-            self.slots.append(slot)
-            return slot
-        return None
+        same = next((s for s in self.slots if s.busy is None and s.key == key), None)
+        need = self._request_bytes(req) + (0 if same is not None else self._slot_bytes(req))
+        # evict idle slots (other than the one to reuse) while the request does
+        # not fit in the budget or no slot is available for a new one
+        while (self.hbm_budget and self._used_bytes() + need > self.hbm_budget) or \
+                (same is None and len(self.slots) >= self.max_slots):
+            idle = [s for s in self.slots if s.busy is None and s is not same]
+            if not idle:
+                return None
+            self.slots.remove(idle[0])
+        if same is not None:
+            return same
+        nz, n, nt, h, w = req.shape
+        proto = Plan(nz, n, nt, h, w, req.tilt, data_dtype=self.data_dtype,
+                     storage_dtype=self.storage_dtype, filter=self.filter, device=self.device)
+        slot = _Slot(key, proto, self.device)
+        self.slots.append(slot)
+        return slot
 
     def _admit(self):
         waiting = collections.deque()
@@ -166,11 +192,15 @@ class Server:
         h = self._host_plan(req)
         proto = slot.proto
         stream = slot.stream
-        # bind the request's tables into the slot's cached buffers on its stream
-        _abi.lamino_plan_bind(h, ctypes.c_void_p(proto.tables.data_ptr()),
-                              ctypes.c_void_p(proto.work.data_ptr()),
-                              ctypes.c_void_p(stream.cuda_stream))
+        # the request's tables go into the slot's device buffer by an
+        # asynchronous upload on the slot's stream; attaching the plan to the
+        # slot's buffers involves no HIP call, so nothing here blocks the host
+        _abi.lamino_plan_table_image(h, ctypes.c_void_p(slot.stage.data_ptr()), slot.stage.numel())
         nz, n = req.shape[0], req.shape[1]
+        with torch.cuda.stream(stream):
+            proto.tables.copy_(slot.stage, non_blocking=True)
+        _abi.lamino_plan_attach(h, ctypes.c_void_p(proto.tables.data_ptr()),
+                                ctypes.c_void_p(proto.work.data_ptr()))
         with torch.cuda.stream(stream):
             if req.data.device.type == "cpu":  # pinned (checked at submission)
                 req._dev_data = req.data.to(self.device, non_blocking=True)
@@ -236,18 +266,27 @@ class Server:
 def run_poisson(server, classes, rate, count, seed=0, tilt_range=(20.0, 40.0)):
     """Submit `count` requests with Poisson arrivals at `rate` per second.
 
-    classes: list of (nz, n, n_theta, h, w, data_tensor); each request draws
-    a class uniformly and a tilt uniformly in tilt_range (degrees)."""
+    classes: list of (nz, n, n_theta, h, w, data); each request draws a class
+    uniformly.  data is either one tensor, used at a tilt drawn uniformly in
+    tilt_range (degrees), or a dict {tilt in degrees: tensor} of data
+    projected at each tilt, from which the request draws a tilt uniformly."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, size=count)
     picks = rng.integers(0, len(classes), size=count)
-    tilts = np.deg2rad(rng.uniform(*tilt_range, size=count))
+    uni = rng.uniform(*tilt_range, size=count)
+    which = rng.random(size=count)
     start = time.perf_counter()
     arrivals = start + np.cumsum(gaps)
     for i in range(count):
         while time.perf_counter() < arrivals[i]:
             server.poll()
         nz, n, nt, h, w, data = classes[picks[i]]
-        server.submit(Request(i, nz, n, nt, h, w, tilts[i], data, arrival=float(arrivals[i])))
+        if isinstance(data, dict):
+            keys = sorted(data)
+            deg = keys[min(int(which[i] * len(keys)), len(keys) - 1)]
+            d = data[deg]
+        else:
+            deg, d = uni[i], data
+        server.submit(Request(i, nz, n, nt, h, w, np.deg2rad(deg), d, arrival=float(arrivals[i])))
     server.drain()
     return server.stats()

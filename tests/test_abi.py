@@ -202,3 +202,75 @@ def test_integer_data_types_are_accepted_for_input(lib):
     o = _abi.lamino_opts_default()
     o.storage_dtype = _abi.LAMINO_U8  # integer types are not storage types
     assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID
+
+
+def test_table_image_and_attach_on_the_host(lib):
+    # the table image is the plan's double-precision tables: identical for two
+    # plans of the same geometry, different for another tilt; attach checks
+    # its buffers and marks the plan bound without any HIP call
+    P = ctypes.c_void_p
+    a = _abi.lamino_plan(_geom(tilt=0.4), _abi.lamino_opts_default())
+    b = _abi.lamino_plan(_geom(tilt=0.4), _abi.lamino_opts_default())
+    c = _abi.lamino_plan(_geom(tilt=0.5), _abi.lamino_opts_default())
+    tb = _abi.lamino_plan_sizes(a)[0]
+    bufs = [ctypes.create_string_buffer(tb) for _ in range(3)]
+    for plan, buf in zip((a, b, c), bufs):
+        _abi.lamino_plan_table_image(plan, ctypes.cast(buf, P), tb)
+    assert bufs[0].raw == bufs[1].raw and bufs[0].raw != bufs[2].raw
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_plan_table_image(a, ctypes.cast(bufs[0], P), tb - 1)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+    for args in ((P(None), P(512)), (P(256), P(None)), (P(256), P(520))):
+        with pytest.raises(_abi.LaminoError) as e:
+            _abi.lamino_plan_attach(a, *args)
+        assert e.value.code == _abi.LAMINO_E_INVALID
+    # attached (not uploaded): a call now passes the host checks; only the
+    # NULL data pointer is refused, before anything is enqueued
+    _abi.lamino_plan_attach(a, P(256), P(512))
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp(a, P(None), P(768), None)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+    for plan in (a, b, c):
+        _abi.lamino_plan_destroy(plan)
+
+
+def test_out_of_core_plan_layout_and_host_checks(lib):
+    # a budget below the device-resident workspace keeps g, then also D, in
+    # host memory; calls check the host buffer and refuse the operations that
+    # need the intermediates on the device, all before any HIP call
+    P = ctypes.c_void_p
+    shape = (24, 40, 50, 24, 40)
+    ref = _abi.lamino_plan(_geom(*shape), _abi.lamino_opts_default())
+    ri = _abi.lamino_plan_info(ref)
+    assert (ri.spill_spectra, ri.spill_slabs, ri.host_bytes) == (0, 0, 0)
+    o = _abi.lamino_opts_default()
+    o.hbm_budget = ri.bytes_spectra // 2
+    plan = _abi.lamino_plan(_geom(*shape), o)
+    pi = _abi.lamino_plan_info(plan)
+    assert (pi.spill_spectra, pi.spill_slabs) == (1, 1)
+    assert pi.work_bytes <= o.hbm_budget
+    assert pi.host_bytes == _a256(ri.bytes_spectra) + _a256(ri.bytes_slabs)
+    hb, io = _abi.lamino_plan_host_sizes(plan)
+    assert (hb, io) == (pi.host_bytes, pi.io_bytes) and io > 0
+    _abi.lamino_plan_attach(plan, P(256), P(512))
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp(plan, P(256), P(512), None)
+    assert e.value.code == _abi.LAMINO_E_UNBOUND
+    for bad in (P(None), P(1000)):
+        with pytest.raises(_abi.LaminoError) as e:
+            _abi.lamino_plan_bind_host(plan, bad)
+        assert e.value.code == _abi.LAMINO_E_INVALID
+    host = ctypes.create_string_buffer(hb + 256)
+    addr = ctypes.addressof(host)
+    _abi.lamino_plan_bind_host(plan, P(addr + (-addr) % 256))
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fwd(plan, P(256), P(512), None)
+    assert e.value.code == _abi.LAMINO_E_UNSUPPORTED
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_admm_tv(plan, P(256), P(512), 0.1, 1.0, 1, 1, 0, P(768), None)
+    assert e.value.code == _abi.LAMINO_E_UNSUPPORTED
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_host(plan, P(256), P(512), P(None), None)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+    for h in (ref, plan):
+        _abi.lamino_plan_destroy(h)

@@ -3,7 +3,9 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import dev
+from helpers import TOL_F32, TOL_LOWP, dev, rel, to_np
+from oracle import filters, nudft
+from oracle.geometry import Geometry
 from paper_2401_11101_amd import Plan
 from paper_2401_11101_amd.serve import Request, Server, run_poisson
 
@@ -43,6 +45,16 @@ def test_request_alone_equals_in_mix(storage):
     diff = float((mixed - alone).abs().max())
     print(f"{storage}: max |in-mix - alone| = {diff:.3e}")
     assert diff <= 1e-6 * float(alone.abs().max())
+    # every served volume against the exact FBP sums at its own shape and tilt
+    tol = TOL_F32 if storage == "f32" else TOL_LOWP
+    worst = 0.0
+    for r in reqs:
+        nz, n, nt, h, w = r.shape
+        g = Geometry(nz=nz, n=n, n_theta=nt, h=h, w=w, phi=r.tilt)
+        e = rel(to_np(r.out), nudft.fbp(to_np(r.data), g, filters.SHEPP_LOGAN))
+        worst = max(worst, e)
+        assert e < tol, (r.rid, e)
+    print(f"{storage}: served volumes vs exact FBP, worst rel-L2 {worst:.2e}")
     srv.close()
 
 
@@ -57,6 +69,25 @@ def test_budget_limits_concurrency():
     srv.drain()
     assert len(srv.finished) == 6
     assert len(srv.slots) == 1
+    srv.close()
+
+
+def test_request_above_budget_is_refused_at_submission():
+    # a request that cannot fit even alone (slot + output volume) raises
+    # instead of waiting forever; the output volume counts against the budget
+    shape = CLASSES[1]
+    probe = Plan(*shape, 0.4, storage_dtype="f16")
+    slot_bytes = probe.tables.numel() + probe.work.numel()
+    out_bytes = shape[0] * shape[1] * shape[1] * 4
+    srv = Server(max_slots=2, hbm_budget=slot_bytes + out_bytes - 1, storage_dtype="f16")
+    with pytest.raises(ValueError):
+        srv.submit(Request(0, *shape, 0.3, _data(shape, 0)))
+    assert not srv.queue and not srv.slots
+    srv.hbm_budget = slot_bytes + out_bytes
+    r = Request(1, *shape, 0.3, _data(shape, 1))
+    srv.submit(r)
+    srv.drain()
+    assert srv.finished == [r]
     srv.close()
 
 
