@@ -371,6 +371,25 @@ int lamino_admm_tv_state_bytes(const lamino_plan_t* plan, size_t* bytes);
 int lamino_admm_tv(const lamino_plan_t* plan, const float* d_data, float* d_vol, double alpha,
                    double rho, int outer, int inner, int resume, void* d_state, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Allocation-free filtered backprojection, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same operation and arguments as
+ * lamino_fbp, but the plan's tables and workspace live in a device array of
+ * LAMINO_SCRATCH_BYTES bytes inside the library (one per device, held from
+ * the first call on that device until the process ends) instead of
+ * caller-bound buffers: the plan need not be bound, and nothing is
+ * allocated.  The caller passes the device input d[n_theta][h][w] and the
+ * output vol[nz][n][n] as for lamino_fbp.  Each call uploads the plan's
+ * table image into the array on `stream` (the plan must outlive the call's
+ * completion).  All calls on one device share the array: calls that overlap
+ * on a device race (serialise them on one stream).  Stage timing
+ * (lamino_plan_profile) does not apply.  Errors: E_INVALID (NULL
+ * arguments), E_BUDGET (table + workspace bytes above LAMINO_SCRATCH_BYTES;
+ * a plan made with opts.hbm_budget well below the limit fits), E_HIP. */
+#define LAMINO_SCRATCH_BYTES (64u << 20)
+int lamino_fbp_noalloc(const lamino_plan_t* plan, const void* d_data, float* d_vol, void* stream);
+
 /* Free the host plan (device buffers stay with the caller). NULL is ok. */
 int lamino_plan_destroy(lamino_plan_t* plan);
 

@@ -49,6 +49,7 @@ EXPORTED = (
     "lamino_tv_shrink",
     "lamino_admm_tv_state_bytes",
     "lamino_admm_tv",
+    "lamino_fbp_noalloc",
 )
 
 
@@ -161,6 +162,7 @@ def load_library(path=LIB_PATH):
     lib.lamino_tv_shrink.argtypes = [P, P, P, P, D, D, I, I, I, P]
     lib.lamino_admm_tv_state_bytes.argtypes = [P, ctypes.POINTER(ctypes.c_size_t)]
     lib.lamino_admm_tv.argtypes = [P, P, P, D, D, I, I, I, P, P]
+    lib.lamino_fbp_noalloc.argtypes = [P, P, P, P]
     for name in ("lamino_plan", "lamino_plan_sizes", "lamino_plan_info", "lamino_plan_bind",
                  "lamino_plan_table_image", "lamino_plan_attach", "lamino_plan_host_sizes",
                  "lamino_plan_bind_host", "lamino_fbp_host",
@@ -168,7 +170,7 @@ def load_library(path=LIB_PATH):
                  "lamino_plan_profile", "lamino_plan_stage_times", "lamino_tv_grad",
                  "lamino_tv_div", "lamino_tv_term", "lamino_tv_shrink", "lamino_direct_work_bytes",
                  "lamino_direct_fbp", "lamino_direct_adj", "lamino_fbp_raw", "lamino_fbp_slices",
-                 "lamino_admm_tv_state_bytes", "lamino_admm_tv"):
+                 "lamino_admm_tv_state_bytes", "lamino_admm_tv", "lamino_fbp_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -327,3 +329,10 @@ def lamino_strerror(code):
 def lamino_last_error():
     return load_library().lamino_last_error().decode()
 
+
+# device scratch of lamino_fbp_noalloc (LAMINO_SCRATCH_BYTES in lamino.h)
+LAMINO_SCRATCH_BYTES = 64 << 20
+
+
+def lamino_fbp_noalloc(plan, d_data, d_vol, stream):
+    _check(load_library().lamino_fbp_noalloc(plan, d_data, d_vol, stream), "lamino_fbp_noalloc")

@@ -16,7 +16,8 @@ LIB = os.path.join(LIBDIR, "liblamino.so")
 SELFTEST = os.path.join(LIBDIR, "lamino_selftest_host")
 CALIB = os.path.join(LIBDIR, "libcopycalib.so")
 
-SOURCES = ["lamino_api.cpp", "lamino_kernels.hip", "lamino_tv.hip", "lamino_direct.hip"]
+SOURCES = ["lamino_api.cpp", "lamino_kernels.hip", "lamino_tv.hip", "lamino_direct.hip",
+           "lamino_scratch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3",

@@ -234,6 +234,31 @@ def test_table_image_and_attach_on_the_host(lib):
         _abi.lamino_plan_destroy(plan)
 
 
+def test_noalloc_fbp_validates_on_the_host(lib):
+    # lamino_fbp_noalloc refuses NULL arguments and plans whose tables and
+    # workspace exceed the library's scratch array before any HIP call
+    P = ctypes.c_void_p
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_noalloc(P(None), P(256), P(512), None)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+    big = _abi.lamino_plan(_geom(256, 256, 400, 256, 256), _abi.lamino_opts_default())
+    info = _abi.lamino_plan_info(big)
+    assert info.work_bytes > _abi.LAMINO_SCRATCH_BYTES
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_noalloc(big, P(256), P(512), None)
+    assert e.value.code == _abi.LAMINO_E_BUDGET
+    assert "scratch" in _abi.lamino_last_error()
+    small = _abi.lamino_plan(_geom(), _abi.lamino_opts_default())
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_noalloc(small, P(None), P(512), None)
+    assert e.value.code == _abi.LAMINO_E_INVALID
+    for plan in (big, small):
+        _abi.lamino_plan_destroy(plan)
+    text = open(HEADER).read()
+    assert f"#define LAMINO_SCRATCH_BYTES (64u << 20)" in text
+    assert _abi.LAMINO_SCRATCH_BYTES == 64 << 20
+
+
 def test_out_of_core_plan_layout_and_host_checks(lib):
     # a budget below the device-resident workspace keeps g, then also D, in
     # host memory; calls check the host buffer and refuse the operations that
@@ -268,6 +293,9 @@ def test_out_of_core_plan_layout_and_host_checks(lib):
     assert e.value.code == _abi.LAMINO_E_UNSUPPORTED
     with pytest.raises(_abi.LaminoError) as e:
         _abi.lamino_admm_tv(plan, P(256), P(512), 0.1, 1.0, 1, 1, 0, P(768), None)
+    assert e.value.code == _abi.LAMINO_E_UNSUPPORTED
+    with pytest.raises(_abi.LaminoError) as e:
+        _abi.lamino_fbp_noalloc(plan, P(256), P(512), None)
     assert e.value.code == _abi.LAMINO_E_UNSUPPORTED
     with pytest.raises(_abi.LaminoError) as e:
         _abi.lamino_fbp_host(plan, P(256), P(512), P(None), None)
