@@ -186,31 +186,38 @@ def _o3_slab(args):
 
 def _exact_columns(args):
     """Exact Fourier FBP sums (oracle O2) of the columns (ys, xs) over the
-    frequency slabs ls: returns sum_l E(x3, l) g_l(column), complex."""
+    frequency slabs ls: sum_l E(x3, l) g_l(column), complex.  The data come
+    from a .npy file; their spectra are formed 16 projections at a time."""
     from threadpoolctl import threadpool_limits
 
-    from oracle import nudft
+    from oracle import filters, nudft
     from oracle.geometry import Geometry, freqs
 
-    ls, G_part, geo, ys, xs = args
+    path, ls, geo, ys, xs = args
     with threadpool_limits(1):
         g = Geometry(**geo)
+        d = np.load(path, mmap_mode="r")
         all_ls = freqs(g.h_p)
+        li = np.array([int(np.where(all_ls == l)[0][0]) for l in ls])
         ms = freqs(g.w_p)
         x1 = np.asarray(xs) - g.n // 2
         x2 = np.asarray(ys) - g.n // 2
-        ct, st = np.cos(g.theta)[:, None], np.sin(g.theta)[:, None]
         ku = (ms / g.w_p)[None, :]
         E = nudft.x3_phases(g, +1.0)
-        out = np.zeros((g.nz, len(xs)), dtype=np.complex128)
-        for k, l in enumerate(ls):
-            kv = l / g.h_p
-            xi1 = (ku * ct + kv * st * np.sin(g.phi)).reshape(-1)
-            xi2 = (ku * st - kv * ct * np.sin(g.phi)).reshape(-1)
-            ph = np.exp(2j * np.pi * (np.outer(xi1, x1) + np.outer(xi2, x2)))
-            gl = G_part[:, k, :].reshape(-1) @ ph
-            out += E[:, int(np.where(all_ls == l)[0][0])][:, None] * gl[None, :]
-        return out
+        gl = np.zeros((len(ls), len(xs)), dtype=np.complex128)
+        for t0 in range(0, g.n_theta, 16):
+            th = g.theta[t0:t0 + 16]
+            gs = Geometry(nz=g.nz, n=g.n, n_theta=len(th), h=g.h, w=g.w, phi=g.phi, theta=th)
+            G = nudft.filter_spectra(nudft.data_spectra_fft(np.asarray(d[t0:t0 + 16]), gs), g,
+                                     filters.SHEPP_LOGAN)[:, li, :]
+            ct, st = np.cos(th)[:, None], np.sin(th)[:, None]
+            for k, l in enumerate(ls):
+                kv = l / g.h_p
+                xi1 = (ku * ct + kv * st * np.sin(g.phi)).reshape(-1)
+                xi2 = (ku * st - kv * ct * np.sin(g.phi)).reshape(-1)
+                ph = np.exp(2j * np.pi * (np.outer(xi1, x1) + np.outer(xi2, x2)))
+                gl[k] += G[:, k, :].reshape(-1) @ ph
+        return E[:, li] @ gl
 
 
 def cpu_baseline(data_np, vols, slabs_per_run=None, runs=3):
@@ -255,11 +262,13 @@ def cpu_baseline(data_np, vols, slabs_per_run=None, runs=3):
         # exact sums on sampled columns against the GPU volumes
         ys = np.array([0, 77, 128, 201])
         xs = np.array([3, 128, 64, 250])
-        G = nudft.filter_spectra(nudft.data_spectra_fft(data_np, g), g, filters.SHEPP_LOGAN)
-        parts = np.array_split(np.arange(len(ls_all)), 4 * workers)
-        jobs = [(ls_all[idx], G[:, idx, :], geo, ys, xs) for idx in parts]
-        del G
-        ref = sum(pool.map(_exact_columns, jobs)).real
+        import tempfile
+
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "data.npy")
+            np.save(path, data_np)
+            parts = np.array_split(ls_all, workers)
+            ref = sum(pool.map(_exact_columns, [(path, part, geo, ys, xs) for part in parts])).real
     rel = {name: float(np.linalg.norm(v[:, ys, xs].astype(np.float64) - ref) / np.linalg.norm(ref))
            for name, v in vols.items()}
     base = {"value": round(NZ * N * N / t_total / 1e9, 9), "unit": "GVoxel/s", "cores": workers,
