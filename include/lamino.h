@@ -144,7 +144,7 @@ void lamino_opts_default(lamino_opts* opts);
  * correction and FFT twiddles in double precision and keeps them on the
  * host until bind.  opts may be NULL (defaults).  On success *out owns a
  * new plan.  Errors: E_INVALID (non-positive sizes, |tilt| >= pi/2,
- * non-finite values, NULL out), E_UNSUPPORTED (a padded size above 4096 or
+ * non-finite values, NULL out), E_UNSUPPORTED (a padded size above 8192 or
  * a grid the FFT kernels do not cover), E_BUDGET (workspace > hbm_budget
  * even at the smallest chunks). */
 int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t** out);

@@ -484,11 +484,11 @@ int lamino_plan(const lamino_geom* geom, const lamino_opts* opts, lamino_plan_t*
   p->h_p = pow2_at_least(std::ceil(o.pad_v * p->h));
   // the gridding works on 32 x 32 matrix-core tiles
   p->grid = std::max(32, pow2_at_least(2.0 * p->n));
-  if (p->w_p < 2 || p->h_p < 2 || p->w_p > 4096 || p->h_p > 4096 || p->grid > 4096) {
+  if (p->w_p < 2 || p->h_p < 2 || p->w_p > 8192 || p->h_p > 8192 || p->grid > 8192) {
     const int wp = p->w_p, hp = p->h_p, gr = p->grid;
     delete p;
     return fail(LAMINO_E_UNSUPPORTED,
-                "lamino_plan: FFT sizes w_p=%d h_p=%d grid=%d outside [2, 4096]", wp, hp, gr);
+                "lamino_plan: FFT sizes w_p=%d h_p=%d grid=%d outside [2, 8192]", wp, hp, gr);
   }
   p->n_slab = p->h_p / 2;
   p->M = o.kernel_m ? o.kernel_m : (o.storage_dtype == LAMINO_F32 ? 5 : 3);

@@ -12,8 +12,14 @@
 namespace lam {
 
 constexpr int NTF = 512;       // threads per block of the FFT kernels
-constexpr int LDS_CPLX = 4096; // complex values per FFT block (one 32 KB buffer)
+constexpr int LDS_CPLX = 4096; // complex values per FFT block up to 4096 points (32 KB)
+constexpr int LDS_CPLX_MAX = 8192;  // the largest transform: one 8192-point block (64 KB)
 constexpr int FFT_IO = LDS_CPLX / NTF;  // loads in flight per thread when staging a block
+
+// Complex values an FFT block holds for transforms of N points (the
+// kernels' dynamic LDS is this many float2 values, several transforms back
+// to back up to 4096 points).
+__host__ __device__ __forceinline__ int fft_capacity(int N) { return N > LDS_CPLX ? N : LDS_CPLX; }
 
 // ------------------------------------------------------------ load/store
 __device__ __forceinline__ float2 ld_c(const void* p, size_t i, int dt) {
@@ -49,18 +55,63 @@ __device__ __forceinline__ float flat_dark_log(float raw, float dark, float flat
 }
 
 // ------------------------------------------------------------ block FFT
+// Order of this wave's LDS accesses (they execute in issue order) without a
+// block barrier: wait for the wave's outstanding LDS operations, and keep the
+// compiler from moving memory accesses across.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // One Stockham pass of radix R over B transforms of length N = 2^log2N in
 // place: each thread reads one butterfly's inputs, twiddles and transforms
-// them in registers, and writes the outputs after a barrier.  N / R <= NTF,
-// so a round covers NTF R / N whole transforms.
-template <int R>
+// them in registers, and writes the outputs after a barrier (a wave-level
+// wait when one wave owns each transform).  N / R <= NTF, so a round covers
+// NTF R / N whole transforms.
+// The same pass when a transform has more butterflies than the block has
+// threads (N = 8192): each thread takes REPS butterflies j = t + NTF rep,
+// reads all of them, and writes after the barrier.
+template <int R, int REPS>
+__device__ __forceinline__ void fft_pass_wide(float2* a, int log2N, int B, int log2Ns,
+                                              const float2* __restrict__ tw, int log2max, bool inv) {
+  const int N = 1 << log2N;
+  const int t = threadIdx.x;
+  for (int bb = 0; bb < B; ++bb) {
+    float2 v[REPS][R];
+#pragma unroll
+    for (int rep = 0; rep < REPS; ++rep) {
+      const int j = t + rep * NTF;
+      if constexpr (R == 8) {
+        r8_load(a + bb * N, N, j, v[rep]);
+        r8_compute(j, log2Ns, tw, log2max, inv, v[rep]);
+      } else if constexpr (R == 4) {
+        r4_load(a + bb * N, N, j, v[rep]);
+        r4_compute(j, log2Ns, tw, log2max, inv, v[rep]);
+      } else {
+        r2_load(a + bb * N, N, j, v[rep]);
+        r2_compute(j, log2Ns, tw, log2max, inv, v[rep]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rep = 0; rep < REPS; ++rep) rstore<R>(a + bb * N, t + rep * NTF, log2Ns, v[rep]);
+    __syncthreads();
+  }
+}
+
+template <int R, bool WIDE>
 __device__ __forceinline__ void fft_pass_inplace(float2* a, int log2N, int B, int log2Ns,
                                                  const float2* __restrict__ tw, int log2max,
-                                                 bool inv) {
+                                                 bool inv, bool wave_local) {
   constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
   const int N = 1 << log2N;
   const int lper = log2N - LR;
   const int per = 1 << lper;
+  if constexpr (WIDE) {
+    if (per > NTF) {  // N = 8192: 1024 (radix 8) or 4096 (radix 2) butterflies
+      if constexpr (R == 8) fft_pass_wide<8, LDS_CPLX_MAX / 8 / NTF>(a, log2N, B, log2Ns, tw, log2max, inv);
+      else if constexpr (R == 4) fft_pass_wide<4, LDS_CPLX_MAX / 4 / NTF>(a, log2N, B, log2Ns, tw, log2max, inv);
+      else fft_pass_wide<2, LDS_CPLX_MAX / 2 / NTF>(a, log2N, B, log2Ns, tw, log2max, inv);
+      return;
+    }
+  }
   const int tb = per >= NTF ? 1 : NTF >> lper;  // transforms per round
   const int t = threadIdx.x;
   const int j = t & (per - 1);
@@ -80,23 +131,34 @@ __device__ __forceinline__ void fft_pass_inplace(float2* a, int log2N, int B, in
         r2_compute(j, log2Ns, tw, log2max, inv, v);
       }
     }
-    __syncthreads();
+    if (wave_local) wave_lds_sync();
+    else __syncthreads();
     if (act) rstore<R>(a + bb * N, j, log2Ns, v);
-    __syncthreads();
+    if (wave_local) wave_lds_sync();
+    else __syncthreads();
   }
 }
 
 // B transforms of length 2^log2N stored back to back in LDS at `a`
-// (B * N <= LDS_CPLX, N <= 4096), transformed in place.
+// (B * N <= fft_capacity(N)), transformed in place.  N <= LDS_CPLX, or
+// N <= LDS_CPLX_MAX with WIDE (a separate kernel instantiation: the wide
+// passes hold 16 values per thread, which would cost every other transform
+// size its occupancy).
+template <bool WIDE>
 __device__ inline void block_fft(float2* a, int log2N, int B, const float2* __restrict__ tw, int log2max,
                           bool inv) {
   const int np = fft_num_passes(log2N);
+  // N = 8, 64, 512: every pass is radix 8 with at most 64 butterflies per
+  // transform, so one wave owns each transform in every pass and the passes
+  // need no block barrier
+  const bool wave_local = log2N % 3 == 0 && log2N <= 9;
   for (int p = 0; p < np; ++p) {
     const FftPass f = fft_pass(log2N, p);
-    if (f.radix == 8) fft_pass_inplace<8>(a, log2N, B, f.log2Ns, tw, log2max, inv);
-    else if (f.radix == 4) fft_pass_inplace<4>(a, log2N, B, f.log2Ns, tw, log2max, inv);
-    else fft_pass_inplace<2>(a, log2N, B, f.log2Ns, tw, log2max, inv);
+    if (f.radix == 8) fft_pass_inplace<8, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+    else if (f.radix == 4) fft_pass_inplace<4, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+    else fft_pass_inplace<2, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
   }
+  if (wave_local) __syncthreads();  // the caller reads across transforms
 }
 
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places

@@ -34,9 +34,10 @@ namespace {
 // patch, whose projection covers a compact detector window at every angle
 constexpr int DB_X = 16, DB_Y = 16, DB_Z = 16, DB_NT = DB_X * DB_Y;
 
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __restrict__ data,
                                                      float* __restrict__ out, int rows, int pairs_per_block) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(w_p) values (launch size)
   const int wp = p.w_p, w = p.w;
   const int pair0 = blockIdx.x * pairs_per_block;
   const int npairs = min(pairs_per_block, (rows + 1) / 2 - pair0);
@@ -55,14 +56,14 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
         bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
       });
   __syncthreads();
-  block_fft(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
+  block_fft<WIDE>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
   for (int e = threadIdx.x; e < npairs * wp; e += NTF) {
     const float f = p.filt_dir[e & (wp - 1)];
     buf[e].x *= f;
     buf[e].y *= f;
   }
   __syncthreads();
-  block_fft(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
+  block_fft<WIDE>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
   for (int e = threadIdx.x; e < nrows * w; e += NTF) {
     const int rr = div24(e, w, iw), c = e - rr * w;
     out[(size_t)row0 * w + e] = bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)];
@@ -224,8 +225,9 @@ hipError_t run_direct(const lamino_plan_s* p, const void* d_data, float* d_vol, 
   if (fbp_filter) {
     const int rows = p->n_theta * p->h;
     const int pairs = (rows + 1) / 2;
-    const int ppb = std::max(1, std::min(LDS_CPLX / p->w_p, 16));
-    hipLaunchKernelGGL(k_dir_filter, dim3((pairs + ppb - 1) / ppb), dim3(NTF), 0, s, kp, d_data,
+    const int ppb = std::max(1, std::min(fft_capacity(p->w_p) / p->w_p, 16));
+    hipLaunchKernelGGL((p->w_p > LDS_CPLX ? k_dir_filter<true> : k_dir_filter<false>), dim3((pairs + ppb - 1) / ppb), dim3(NTF),
+                       (size_t)fft_capacity(p->w_p) * sizeof(float2), s, kp, d_data,
                        static_cast<float*>(d_work), rows, ppb);
     src = d_work;
     dt = LAMINO_F32;

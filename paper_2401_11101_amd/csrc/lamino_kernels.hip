@@ -38,10 +38,11 @@ constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 // complex h_p-point FFT along v; the two real spectra are separated by
 // Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
 // data holds projections data_th0 .. (a whole input or a streamed chunk).
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
                                                       int cp, int data_th0) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int c0 = blockIdx.x * 2 * cp;
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
         bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
       });
   __syncthreads();
-  block_fft(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
+  block_fft<WIDE>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   for (int e = threadIdx.x; e < p.n_slab * wide; e += NTF) {
@@ -89,11 +90,12 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 // Rows l of the column spectra: w_p-point FFT along u, times the transfer
 // function, stored as D[l][theta - d_th0][k] (k = m mod w_p) with d_nth
 // projections per slab (all of them, or one streamed chunk).
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
                                                       const float2* __restrict__ phase, int theta0,
                                                       int rows, int d_nth, int d_th0) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
         buf[b * wp + ((c - p.w / 2) & (wp - 1))] = v;
       });
   __syncthreads();
-  block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
+  block_fft<WIDE>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e >> p.log2_wp, k = e & (wp - 1);
@@ -136,10 +138,11 @@ __global__ void k_axis_phase(float2* __restrict__ out, int wp, double delta) {
 
 // Inverse of the row step (forward projection): D[l][theta][.] -> inverse
 // FFT along m -> detector columns, W1[theta_local][l][c].
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
                                                       float2* __restrict__ w1, int theta0,
                                                       int rows) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
       },
       [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  block_fft(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
+  block_fft<WIDE>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   const float iw = 1.f / (float)p.w;
@@ -172,10 +175,11 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
 // l = 0 dropped), packed as Z = X_c + i X_{c+1}, inverse transformed along
 // v, and the real / imaginary parts scaled by 1/(h_p w_p) give the two
 // detector columns.
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ data, int theta0,
                                                       int cp, float scale) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   const int c0 = blockIdx.x * 2 * cp;
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
         }
       });
   __syncthreads();
-  block_fft(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
+  block_fft<WIDE>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int wide = 2 * cp;
   const float iwide = 1.f / (float)wide;
@@ -331,9 +335,9 @@ struct SpreadCand {
 // PREC 0: bf16 x3 (float32 storage), 1: float16 x1, 2: bfloat16 x1
 template <int M, int PREC>
 __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
-                                               float2* __restrict__ G, int slab0, int d_l0) {
+                                               float2* __restrict__ G, int slab0, int d_l0, int ns) {
   constexpr int W = 2 * M;
-  constexpr int WS = W + 2;  // slot: zero, W taps, zero
+  constexpr int WS = W + 3;  // slot: zero, W taps, zero, pad (an odd stride in 32-bit words)
   // row weight: bf16 hi | lo (PREC 0) or one 16-bit value; column value:
   // (re, im) as hi | lo words (PREC 0) or re | im << 16
   typedef typename std::conditional<PREC == 0, unsigned, unsigned short>::type TA;
@@ -343,10 +347,11 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   __shared__ TA st_a[64 * WS];
   __shared__ TB st_b[64 * WS];
   const int lane = threadIdx.x;
-  const int l = slab0 + blockIdx.x;  // slabs vary fastest, dense central tiles first
+  const int sl = (int)(blockIdx.x % (unsigned)ns);  // slabs vary fastest, dense central tiles first
+  const int l = slab0 + sl;
   const int ntx = p.grid / SP_T;
   int tx, ty;
-  ring_tile(blockIdx.y, ntx, tx, ty);
+  ring_tile((int)(blockIdx.x / (unsigned)ns), ntx, tx, ty);
   const int X0 = -(p.grid >> 1) + tx * SP_T;
   const int Y0 = -(p.grid >> 1) + ty * SP_T;
   const float gcl = p.gs * (float)l;
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
     }
   }
   // accumulator v of lane: tile row 8 (v / 4) + 4 (lane / 32) + v % 4, column lane % 32
-  float2* g = G + (size_t)blockIdx.x * p.grid * p.grid;
+  float2* g = G + (size_t)sl * p.grid * p.grid;
   const int kx = (X0 + r) & (p.grid - 1);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -519,9 +524,9 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   }
 }
 
-// Forward USFFT step (3): interpolate slab (slab0 + blockIdx.x) of the grid
+// Forward USFFT step (3): interpolate slab slab0 + (block % ns) of the grid
 // at the samples whose wrapped base cell floor(X), floor(Y) lies in tile
-// ring_tile(blockIdx.y); the padded tile is staged in LDS.  Each sample has exactly
+// ring_tile(block / ns); the padded tile is staged in LDS.  Each sample has exactly
 // one owner tile, so D is written once per sample.  The block's four waves
 // take interleaved passes of 64 angles; a pass finds the m-interval of each
 // angle that can own samples in the tile (box widened by one cell), compacts
@@ -529,23 +534,24 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
 // 64 at a time, one per lane.
 template <int M>
 __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restrict__ G,
-                                               void* __restrict__ D, int slab0, int tile) {
+                                               void* __restrict__ D, int slab0, int tile, int ns) {
   constexpr int W = 2 * M;
   constexpr int PMAX = TILE_MAX + W - 1;
   constexpr int NW = NT / 64;
   __shared__ float2 st[PMAX * PMAX];
   const int P = tile + W - 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l = slab0 + blockIdx.x;  // slabs vary fastest, dense central tiles first
+  const int sl = (int)(blockIdx.x % (unsigned)ns);  // slabs vary fastest, dense central tiles first
+  const int l = slab0 + sl;
   const int ntx = p.grid / tile;
   int tx, ty;
-  ring_tile(blockIdx.y, ntx, tx, ty);
+  ring_tile((int)(blockIdx.x / (unsigned)ns), ntx, tx, ty);
   const int X0 = -(p.grid >> 1) + tx * tile;
   const int Y0 = -(p.grid >> 1) + ty * tile;
   const float gcl = p.gs * (float)l;
   const float e2b = __expf(-2.f * p.beta);
   const int half_m = (p.w_p >> 1) - 1;
-  const size_t gbase = (size_t)blockIdx.x * p.grid * p.grid;
+  const size_t gbase = (size_t)sl * p.grid * p.grid;
   const float iP = 1.f / (float)P;
   for (int e = threadIdx.x; e < P * P; e += NT) {
     const int yy = div24(e, P, iP), xx = e - yy * P;
@@ -639,9 +645,10 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
 
 // Inverse FFT along x1 of each gridded slab row; the first n entries of
 // the row then hold x1 = ix - n/2.
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
                                                       int rows) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
@@ -649,7 +656,7 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
       min(rows, N - r0) * N, [&](int e) { return g[(size_t)r0 * N + e]; },
       [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
+  block_fft<WIDE>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const float in = 1.f / (float)p.n;
   for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
@@ -659,10 +666,11 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
 }
 
 // g holds slabs g_l0 .. (all of them, or one streamed chunk).
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
                                                       void* __restrict__ g, int slab0, int cols,
                                                       int g_l0) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float icols = 1.f / (float)cols;
@@ -678,7 +686,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
         buf[c * N + k2] = v;
       });
   __syncthreads();
-  block_fft(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
+  block_fft<WIDE>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int l = slab0 + blockIdx.y;
   for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
@@ -690,9 +698,10 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   }
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float icols = 1.f / (float)cols;
@@ -712,7 +721,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
         if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
       });
   __syncthreads();
-  block_fft(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
+  block_fft<WIDE>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   float2* gg = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < cols * N; e += NTF) {
@@ -721,9 +730,10 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
   }
 }
 
+template <bool WIDE>
 __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
                                                       int rows) {
-  __shared__ float2 buf[LDS_CPLX];
+  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
   const int N = p.grid;
   const int r0 = blockIdx.x * rows;
   float2* g = G + (size_t)blockIdx.y * N * N;
@@ -741,7 +751,7 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
         buf[b * N + ((ix - p.n / 2) & (N - 1))] = v;
       });
   __syncthreads();
-  block_fft(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
+  block_fft<WIDE>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e >> p.log2_grid;
@@ -1017,6 +1027,10 @@ __global__ __launch_bounds__(256) void k_absmax_final(float* __restrict__ dyn, i
 // ================================================================ drivers
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// The instantiation of an FFT kernel for transforms of N points (the wide
+// passes only where N exceeds LDS_CPLX).
+#define FFT_KERNEL(k, N) ((N) > LDS_CPLX ? k<true> : k<false>)
+
 // Sets the float16 input factor of a call from its input (x != NULL) or from
 // a known bound alone.
 // Block maxima of x[0 .. n) into dyn[2 ..] (nb blocks); with accumulate the
@@ -1048,23 +1062,40 @@ static void input_factor(const KParams& kp, const void* x, size_t n, int dt, flo
 
 static int spread_tile(const KParams& p) { return p.grid <= 128 ? (p.grid < 32 ? p.grid : 32) : 64; }
 
-// D holds slabs d_l0 .. (all of them, or one streamed chunk)
+// Gridding launches are one-dimensional (block = slab + ns * tile rank) and
+// hold at most GRID_BLOCKS_MAX blocks: larger slab chunks go in several
+// launches of fewer slabs (grid 8192 has 65536 spreading tiles per slab).
+constexpr int GRID_BLOCKS_MAX = 1 << 22;
+
+// D holds slabs d_l0 .. (all of them, or one streamed chunk); G the planes
+// of slabs s0 .. s0 + ns - 1
 template <int M>
 static void launch_spread(const KParams& kp, const void* D, float2* G, int s0, int ns, int d_l0,
                           hipStream_t s) {
   const int tiles = (kp.grid / SP_T) * (kp.grid / SP_T);
-  if (kp.storage_dtype == LAMINO_F32)
-    hipLaunchKernelGGL((k_spread<M, 0>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
-  else if (kp.storage_dtype == LAMINO_F16)
-    hipLaunchKernelGGL((k_spread<M, 1>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
-  else
-    hipLaunchKernelGGL((k_spread<M, 2>), dim3(ns, tiles), dim3(64), 0, s, kp, D, G, s0, d_l0);
+  const int per = std::max(1, std::min(ns, GRID_BLOCKS_MAX / tiles));
+  for (int j = 0; j < ns; j += per) {
+    const int nj = std::min(per, ns - j);
+    float2* Gj = G + (size_t)j * kp.grid * kp.grid;
+    const dim3 grid((unsigned)nj * (unsigned)tiles);
+    if (kp.storage_dtype == LAMINO_F32)
+      hipLaunchKernelGGL((k_spread<M, 0>), grid, dim3(64), 0, s, kp, D, Gj, s0 + j, d_l0, nj);
+    else if (kp.storage_dtype == LAMINO_F16)
+      hipLaunchKernelGGL((k_spread<M, 1>), grid, dim3(64), 0, s, kp, D, Gj, s0 + j, d_l0, nj);
+    else
+      hipLaunchKernelGGL((k_spread<M, 2>), grid, dim3(64), 0, s, kp, D, Gj, s0 + j, d_l0, nj);
+  }
 }
 template <int M>
 static void launch_interp(const KParams& kp, const float2* G, void* D, int s0, int ns, int tile,
                           hipStream_t s) {
   const int tiles = (kp.grid / tile) * (kp.grid / tile);
-  hipLaunchKernelGGL(k_interp<M>, dim3(ns, tiles), dim3(NT), 0, s, kp, G, D, s0, tile);
+  const int per = std::max(1, std::min(ns, GRID_BLOCKS_MAX / tiles));
+  for (int j = 0; j < ns; j += per) {
+    const int nj = std::min(per, ns - j);
+    hipLaunchKernelGGL(k_interp<M>, dim3((unsigned)nj * (unsigned)tiles), dim3(NT), 0, s, kp,
+                       G + (size_t)j * kp.grid * kp.grid, D, s0 + j, tile, nj);
+  }
 }
 
 static void spread_dispatch(const KParams& kp, const void* D, float2* G, int s0, int ns, int d_l0,
@@ -1191,8 +1222,11 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   char* hg = hsp + p->off_hg;
 
   // ---- detector stage: per projection chunk
-  const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
-  const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
+  const int cp = std::min(fft_capacity(p->h_p) / p->h_p, std::max(1, (p->w + 1) / 2));
+  const int rows_w = std::min(fft_capacity(p->w_p) / p->w_p, p->n_slab);
+  const size_t lds_h = (size_t)fft_capacity(p->h_p) * sizeof(float2);
+  const size_t lds_w = (size_t)fft_capacity(p->w_p) * sizeof(float2);
+  const size_t lds_g = (size_t)fft_capacity(p->grid) * sizeof(float2);
   for (int t0 = 0, c = 0; t0 < p->n_theta; t0 += p->theta_chunk, ++c) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     const void* src = d_data;
@@ -1217,10 +1251,10 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     }
     {
       StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2, timing);
-      hipLaunchKernelGGL(k_proj_cols_fwd, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp, src,
+      hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_fwd, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp, src,
                          W1, t0, cp, src_th0);
       if (host_in) rec(2 + (c & 1), s);
-      hipLaunchKernelGGL(k_proj_rows_fwd, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
+      hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_fwd, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
                          (const float2*)W1, Dt, kp.filt, (const float2*)phase, t0, rows_w, d_nth,
                          d_th0);
     }
@@ -1242,8 +1276,8 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   }
 
   // ---- gridding and slab stages: per slab chunk
-  const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
-  const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
+  const int rows_g = std::min(fft_capacity(p->grid) / p->grid, p->grid);
+  const int cols_g = std::min(fft_capacity(p->grid) / p->grid, p->n);
   for (int s0 = 0, j = 0; s0 < p->n_slab; s0 += p->slab_chunk, ++j) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     const void* Dg = D;
@@ -1272,9 +1306,9 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     }
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2, timing);
-      hipLaunchKernelGGL(k_grid_rows_inv, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp, G,
+      hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_inv, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp, G,
                          rows_g);
-      hipLaunchKernelGGL(k_grid_cols_adj, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
+      hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
                          (const float2*)G, gt, s0, cols_g, g_l0);
     }
     if (p->spill_g) {
@@ -1371,30 +1405,33 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
     hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, 32), cdiv(2 * p->n_slab, X3_ROWS)),
                        dim3(64 * X3_WAVES), 0, s, kp, d_vol, g);
   }
-  const int rows_g = std::min(LDS_CPLX / p->grid, p->grid);
-  const int cols_g = std::min(LDS_CPLX / p->grid, p->n);
+  const int rows_g = std::min(fft_capacity(p->grid) / p->grid, p->grid);
+  const int cols_g = std::min(fft_capacity(p->grid) / p->grid, p->n);
+  const size_t lds_h = (size_t)fft_capacity(p->h_p) * sizeof(float2);
+  const size_t lds_w = (size_t)fft_capacity(p->w_p) * sizeof(float2);
+  const size_t lds_g = (size_t)fft_capacity(p->grid) * sizeof(float2);
   for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
-      hipLaunchKernelGGL(k_grid_cols_fwd, dim3(cdiv(p->n, cols_g), ns), dim3(NTF), 0, s, kp,
+      hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
                          (const void*)g, G, s0, cols_g);
-      hipLaunchKernelGGL(k_grid_rows_fwd, dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), 0, s, kp,
+      hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_fwd, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp,
                          G, rows_g);
     }
     StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
     interp_dispatch(kp, G, D, s0, ns, s);
   }
-  const int cp = std::min(LDS_CPLX / p->h_p, std::max(1, (p->w + 1) / 2));
-  const int rows_w = std::min(LDS_CPLX / p->w_p, p->n_slab);
+  const int cp = std::min(fft_capacity(p->h_p) / p->h_p, std::max(1, (p->w + 1) / 2));
+  const int rows_w = std::min(fft_capacity(p->w_p) / p->w_p, p->n_slab);
   // 1 / (h_p w_p) of the inverse DFT, and the static float16 factors removed
   const float scale = (float)(1.0 / ((double)p->h_p * p->w_p) / ((double)kp.fwd_g_scale * kp.fwd_D_scale));
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
-    hipLaunchKernelGGL(k_proj_rows_inv, dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), 0, s, kp,
+    hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_inv, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
                        (const void*)D, W1, t0, rows_w);
-    hipLaunchKernelGGL(k_proj_cols_inv, dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), 0, s, kp,
+    hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_inv, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp,
                        (const float2*)W1, d_data, t0, cp, scale);
   }
   return hipGetLastError();

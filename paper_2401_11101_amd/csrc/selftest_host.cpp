@@ -2,7 +2,7 @@
 //
 //  fft     Stockham radix-8/4/2 passes of lamino_common.h, run serially over
 //          ping-pong buffers, against a naive double-precision DFT for
-//          N = 2 .. 4096, both directions.
+//          N = 2 .. 8192, both directions.
 //  cand    for random slabs, angles and tiles: every sample whose Gaussian
 //          taps reach a tile copy lies in that copy's candidate m-interval
 //          (gridding), and every sample is owned by exactly one tile through
@@ -27,7 +27,7 @@
 using namespace lam;
 
 static int check_fft() {
-  const int log2max = 12;
+  const int log2max = 13;
   const int Nmax = 1 << log2max;
   std::vector<float2> tw(Nmax);
   for (int t = 0; t < Nmax; ++t) {

@@ -85,7 +85,7 @@ def test_plan_rejects_bad_geometry(lib):
     assert _plan_status(_geom(tilt=math.pi / 2)) == _abi.LAMINO_E_INVALID
     assert _plan_status(_geom(tilt=float("nan"))) == _abi.LAMINO_E_INVALID
     assert _plan_status(_geom(w=5000)) == _abi.LAMINO_E_UNSUPPORTED
-    assert _plan_status(_geom(n=3000)) == _abi.LAMINO_E_UNSUPPORTED
+    assert _plan_status(_geom(n=5000)) == _abi.LAMINO_E_UNSUPPORTED
     o = _abi.lamino_opts_default()
     o.kernel_m = 1
     assert _plan_status(_geom(), o) == _abi.LAMINO_E_INVALID

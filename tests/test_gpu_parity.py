@@ -364,17 +364,20 @@ def test_steep_tilts(phi):
     assert ef < TOL_F32 and ea < TOL_F32 and eb < TOL_F32
 
 
-@pytest.mark.parametrize("nz, n, nt, h, w", [(4, 2048, 6, 6, 2048), (8, 24, 5, 2048, 20)])
-def test_largest_fft_sizes_adjoint_and_chunking(nz, n, nt, h, w):
-    # the largest transforms the plan accepts: detector rows padded to
-    # w_p = 4096 with slab grids of N_g = 4096 (n = 2048), and detector
-    # columns padded to h_p = 4096 (2048 frequency slabs, one column pair per
-    # transform block).  The exact sums are out of reach at these sizes, so
-    # the check is the adjoint identity <L f, d> = <f, L* d> in FP64 and
-    # chunked == unchunked.
+@pytest.mark.parametrize("nz, n, nt, h, w, size", [
+    (4, 2048, 6, 6, 2048, 4096), (8, 24, 5, 2048, 20, 4096),
+    (2, 4096, 4, 4, 4096, 8192), (4, 24, 5, 4096, 20, 8192)])
+def test_largest_fft_sizes_adjoint_and_chunking(nz, n, nt, h, w, size):
+    # transforms of 4096 points (several per LDS block) and of 8192, the
+    # largest the plan accepts (one per block, more butterflies than
+    # threads): detector rows padded to w_p = size with slab grids of
+    # N_g = size (n = size / 2), and detector columns padded to h_p = size
+    # (size / 2 frequency slabs, one column pair per transform block).  The
+    # exact sums are out of reach at these sizes, so the check is the adjoint
+    # identity <L f, d> = <f, L* d> in FP64 and chunked == unchunked.
     tilt = np.deg2rad(30.0)
     plan = Plan(nz, n, nt, h, w, tilt)
-    assert 4096 in (plan.info.w_p, plan.info.h_p)
+    assert size == max(plan.info.w_p, plan.info.h_p)
     print(f"max sizes: w_p {plan.info.w_p}, h_p {plan.info.h_p}, grid {plan.info.grid}", flush=True)
     gen = torch.Generator(device=dev()).manual_seed(3)
     f = torch.rand((nz, n, n), device=dev(), generator=gen) - 0.5
@@ -389,3 +392,30 @@ def test_largest_fft_sizes_adjoint_and_chunking(nz, n, nt, h, w):
     small = Plan(nz, n, nt, h, w, tilt, z_chunk=3, slab_chunk=1, theta_chunk=4)
     assert rel(to_np(small.adj(d)), to_np(ld)) < 1e-6
     assert rel(to_np(small.fwd(f)), to_np(lf)) < 1e-6
+
+
+def test_8192_point_transforms_against_oracle():
+    # the largest transforms against the exact sums: detector rows padded to
+    # w_p = 8192 with slab grids of 8192 (FBP on sampled columns), then
+    # detector columns padded to h_p = 8192 (4096 frequency slabs; FBP, L*
+    # and L on the whole small volume)
+    g, plan, _, d = _pair(2, 4096, 4, 4, 4096, 30, seed=7)
+    assert (plan.info.w_p, plan.info.grid) == (8192, 8192)
+    print("w_p 8192, grid 8192: sampled FBP columns", flush=True)
+    vol = to_np(plan.fbp(to_dev(d)))
+    G = nudft.filter_spectra(nudft.data_spectra_fft(d, g), g, filters.SHEPP_LOGAN)
+    ys = np.array([0, 1111, 2048, 2049, 3001, 4095])
+    xs = np.array([4095, 17, 2048, 1999, 3500, 0])
+    e = rel(vol[:, ys, xs], nudft.backproject_columns(G, g, ys, xs))
+    print(f"  rel-L2 {e:.2e}", flush=True)
+    assert e < TOL_F32
+    g, plan, f, d = _pair(4, 24, 5, 4096, 20, 30, seed=8)
+    assert plan.info.h_p == 8192
+    print("h_p 8192: FBP, L*, L", flush=True)
+    G = nudft.data_spectra_fft(d, g)
+    eb = rel(to_np(plan.fbp(to_dev(d))),
+             nudft.backproject_spectra(nudft.filter_spectra(G, g, filters.SHEPP_LOGAN), g))
+    ea = rel(to_np(plan.adj(to_dev(d))), nudft.backproject_spectra(G, g))
+    ef = rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g))
+    print(f"  fbp {eb:.2e} adj {ea:.2e} fwd {ef:.2e}", flush=True)
+    assert eb < TOL_F32 and ea < TOL_F32 and ef < TOL_F32
