@@ -57,10 +57,10 @@ struct FftPass {
   int log2Ns;  // log2 of the sub-transform size before this pass
 };
 
-LAM_HD int fft_num_passes(int log2N) { return log2N / 3 + (log2N % 3 ? 1 : 0); }
+constexpr LAM_HD int fft_num_passes(int log2N) { return log2N / 3 + (log2N % 3 ? 1 : 0); }
 
-LAM_HD FftPass fft_pass(int log2N, int p) {
-  FftPass f;
+constexpr LAM_HD FftPass fft_pass(int log2N, int p) {
+  FftPass f{};
   const int n8 = log2N / 3;
   if (p < n8) {
     f.radix = 8;
@@ -205,8 +205,13 @@ LAM_HD void sample_pos(float ncw, float gcl, float2 cs, int m, float& X, float& 
   Y = fmaf(ncw * cs.y, fm, -(gcl * cs.x));
 }
 
-// m-interval of samples whose coordinate a m + b lies in [lo, hi).
-// Conservative by one sample at each end; returns false if empty.
+// m-interval of samples whose coordinate a m + b lies in [lo, hi), as
+// sample_pos computes it (one fma); returns false if empty.  Conservative:
+// the bounds t0, t1 carry three roundings (relative 2^-24 each), and a
+// sample's computed coordinate is off by at most 2^-24 of its magnitude,
+// i.e. by that over |a| in m.  floor / ceil absorb a total error below one
+// sample; the margin mg adds whole samples beyond that (4x the bound), and
+// is 0 unless |a| is tiny.
 LAM_HD bool coord_interval(float a, float b, float lo, float hi, int& mlo, int& mhi) {
   if (fabsf(a) < 1e-6f) {
     if (b >= lo - 1.0f && b < hi + 1.0f) {
@@ -216,8 +221,6 @@ LAM_HD bool coord_interval(float a, float b, float lo, float hi, int& mlo, int& 
     }
     return false;
   }
-  // one division: the products carry at most ~1e-7 relative error, far
-  // inside the one-sample margin below for every |m| the grids can reach
   const float ia = 1.0f / a;
   float t0 = (lo - b) * ia, t1 = (hi - b) * ia;
   if (t0 > t1) {
@@ -228,8 +231,11 @@ LAM_HD bool coord_interval(float a, float b, float lo, float hi, int& mlo, int& 
   // clamp before the conversion so that nothing overflows an int
   t0 = fmaxf(t0, -1.0e8f);
   t1 = fminf(t1, 1.0e8f);
-  mlo = (int)floorf(t0) - 1;
-  mhi = (int)ceilf(t1) + 1;
+  const float xmax = fmaxf(fabsf(lo), fabsf(hi)) + 1.0f;
+  const float err = 4.0f * (6.0e-8f * xmax * fabsf(ia) + 1.8e-7f * fmaxf(fabsf(t0), fabsf(t1)));
+  const int mg = (int)fminf(err, 1.0e6f);
+  mlo = (int)floorf(t0) - mg;
+  mhi = (int)ceilf(t1) + mg;
   return mlo <= mhi;
 }
 

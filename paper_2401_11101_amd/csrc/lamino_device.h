@@ -140,25 +140,42 @@ __device__ __forceinline__ void fft_pass_inplace(float2* a, int log2N, int B, in
 }
 
 // B transforms of length 2^log2N stored back to back in LDS at `a`
-// (B * N <= fft_capacity(N)), transformed in place.  N <= LDS_CPLX, or
-// N <= LDS_CPLX_MAX with WIDE (a separate kernel instantiation: the wide
-// passes hold 16 values per thread, which would cost every other transform
-// size its occupancy).
-template <bool WIDE>
+// (B * N <= fft_capacity(N)), transformed in place.  LOGN > 0 fixes log2N at
+// compile time (the passes unroll, their index arithmetic folds); LOGN = 0
+// takes log2N at run time (N <= LDS_CPLX).  N > LDS_CPLX (8192 points) has
+// its own instantiation: its wide passes hold 16 values per thread, which
+// would cost every other transform size its occupancy.
+template <int LOGN, int P>
+__device__ __forceinline__ void block_fft_fixed(float2* a, int B, const float2* __restrict__ tw,
+                                                int log2max, bool inv) {
+  if constexpr (P < fft_num_passes(LOGN)) {
+    constexpr FftPass f = fft_pass(LOGN, P);
+    // N = 8, 64, 512: every pass is radix 8 with at most 64 butterflies per
+    // transform, so one wave owns each transform in every pass and the
+    // passes need no block barrier
+    constexpr bool wave_local = LOGN % 3 == 0 && LOGN <= 9;
+    fft_pass_inplace<f.radix, (LOGN > 12)>(a, LOGN, B, f.log2Ns, tw, log2max, inv, wave_local);
+    block_fft_fixed<LOGN, P + 1>(a, B, tw, log2max, inv);
+  }
+}
+
+template <int LOGN>
 __device__ inline void block_fft(float2* a, int log2N, int B, const float2* __restrict__ tw, int log2max,
                           bool inv) {
-  const int np = fft_num_passes(log2N);
-  // N = 8, 64, 512: every pass is radix 8 with at most 64 butterflies per
-  // transform, so one wave owns each transform in every pass and the passes
-  // need no block barrier
-  const bool wave_local = log2N % 3 == 0 && log2N <= 9;
-  for (int p = 0; p < np; ++p) {
-    const FftPass f = fft_pass(log2N, p);
-    if (f.radix == 8) fft_pass_inplace<8, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
-    else if (f.radix == 4) fft_pass_inplace<4, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
-    else fft_pass_inplace<2, WIDE>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+  if constexpr (LOGN > 0) {
+    block_fft_fixed<LOGN, 0>(a, B, tw, log2max, inv);
+    if constexpr (LOGN % 3 == 0 && LOGN <= 9) __syncthreads();  // the caller reads across transforms
+  } else {
+    const int np = fft_num_passes(log2N);
+    const bool wave_local = log2N % 3 == 0 && log2N <= 9;
+    for (int p = 0; p < np; ++p) {
+      const FftPass f = fft_pass(log2N, p);
+      if (f.radix == 8) fft_pass_inplace<8, false>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+      else if (f.radix == 4) fft_pass_inplace<4, false>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+      else fft_pass_inplace<2, false>(a, log2N, B, f.log2Ns, tw, log2max, inv, wave_local);
+    }
+    if (wave_local) __syncthreads();  // the caller reads across transforms
   }
-  if (wave_local) __syncthreads();  // the caller reads across transforms
 }
 
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places

@@ -34,7 +34,7 @@ namespace {
 // patch, whose projection covers a compact detector window at every angle
 constexpr int DB_X = 16, DB_Y = 16, DB_Z = 16, DB_NT = DB_X * DB_Y;
 
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __restrict__ data,
                                                      float* __restrict__ out, int rows, int pairs_per_block) {
   extern __shared__ float2 buf[];  // fft_capacity(w_p) values (launch size)
@@ -56,14 +56,14 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
         bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
+  block_fft<LOGN>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
   for (int e = threadIdx.x; e < npairs * wp; e += NTF) {
     const float f = p.filt_dir[e & (wp - 1)];
     buf[e].x *= f;
     buf[e].y *= f;
   }
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
+  block_fft<LOGN>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, true);
   for (int e = threadIdx.x; e < nrows * w; e += NTF) {
     const int rr = div24(e, w, iw), c = e - rr * w;
     out[(size_t)row0 * w + e] = bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)];
@@ -226,7 +226,7 @@ hipError_t run_direct(const lamino_plan_s* p, const void* d_data, float* d_vol, 
     const int rows = p->n_theta * p->h;
     const int pairs = (rows + 1) / 2;
     const int ppb = std::max(1, std::min(fft_capacity(p->w_p) / p->w_p, 16));
-    hipLaunchKernelGGL((p->w_p > LDS_CPLX ? k_dir_filter<true> : k_dir_filter<false>), dim3((pairs + ppb - 1) / ppb), dim3(NTF),
+    hipLaunchKernelGGL((p->w_p > LDS_CPLX ? k_dir_filter<13> : k_dir_filter<0>), dim3((pairs + ppb - 1) / ppb), dim3(NTF),
                        (size_t)fft_capacity(p->w_p) * sizeof(float2), s, kp, d_data,
                        static_cast<float*>(d_work), rows, ppb);
     src = d_work;

@@ -38,7 +38,7 @@ constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 // complex h_p-point FFT along v; the two real spectra are separated by
 // Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
 // data holds projections data_th0 .. (a whole input or a streamed chunk).
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
                                                       int cp, int data_th0) {
@@ -71,7 +71,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
         bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
+  block_fft<LOGN>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   for (int e = threadIdx.x; e < p.n_slab * wide; e += NTF) {
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 // Rows l of the column spectra: w_p-point FFT along u, times the transfer
 // function, stored as D[l][theta - d_th0][k] (k = m mod w_p) with d_nth
 // projections per slab (all of them, or one streamed chunk).
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ D, const float* filt,
                                                       const float2* __restrict__ phase, int theta0,
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
         buf[b * wp + ((c - p.w / 2) & (wp - 1))] = v;
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
+  block_fft<LOGN>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * wp; e += NTF) {
     const int b = e >> p.log2_wp, k = e & (wp - 1);
@@ -138,7 +138,7 @@ __global__ void k_axis_phase(float2* __restrict__ out, int wp, double delta) {
 
 // Inverse of the row step (forward projection): D[l][theta][.] -> inverse
 // FFT along m -> detector columns, W1[theta_local][l][c].
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __restrict__ D,
                                                       float2* __restrict__ w1, int theta0,
                                                       int rows) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
       },
       [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
+  block_fft<LOGN>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   const float iw = 1.f / (float)p.w;
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
 // l = 0 dropped), packed as Z = X_c + i X_{c+1}, inverse transformed along
 // v, and the real / imaginary parts scaled by 1/(h_p w_p) give the two
 // detector columns.
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* __restrict__ w1,
                                                       void* __restrict__ data, int theta0,
                                                       int cp, float scale) {
@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
         }
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
+  block_fft<LOGN>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int wide = 2 * cp;
   const float iwide = 1.f / (float)wide;
@@ -387,8 +387,8 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
         const int th = th0 + lane;
         int mlo = 0, mhi = -1;
         const bool found = th < p.n_theta &&
-                           tile_candidates(p.ncw, gcl, p.trig[th], bx0, by0, (float)(SP_T + 2 * M),
-                                           (float)(SP_T + 2 * M), half_m, mlo, mhi);
+                           tile_candidates(p.ncw, gcl, p.trig[th], bx0, by0, (float)(SP_T + 2 * M - 1),
+                                           (float)(SP_T + 2 * M - 1), half_m, mlo, mhi);
         const unsigned long long fm = __ballot(found);
         const int nseg = __popcll(fm);
         if (nseg == 0) continue;
@@ -529,7 +529,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
 // ring_tile(block / ns); the padded tile is staged in LDS.  Each sample has exactly
 // one owner tile, so D is written once per sample.  The block's four waves
 // take interleaved passes of 64 angles; a pass finds the m-interval of each
-// angle that can own samples in the tile (box widened by one cell), compacts
+// angle that can own samples in the tile (the tile's own box), compacts
 // the non-empty intervals over the wave's lanes, and walks the candidates
 // 64 at a time, one per lane.
 template <int M>
@@ -576,8 +576,8 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
         const int th = th0 + lane;
         int mlo = 0, mhi = -1;
         const bool found =
-            th < p.n_theta && tile_candidates(p.ncw, gcl, p.trig[th], (float)(ox - 1), (float)(oy - 1),
-                                              (float)(tile + 2), (float)(tile + 2), half_m, mlo, mhi);
+            th < p.n_theta && tile_candidates(p.ncw, gcl, p.trig[th], (float)ox, (float)oy,
+                                              (float)tile, (float)tile, half_m, mlo, mhi);
         const unsigned long long fm = __ballot(found);
         const int nseg = __popcll(fm);
         if (nseg == 0) continue;
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
 
 // Inverse FFT along x1 of each gridded slab row; the first n entries of
 // the row then hold x1 = ix - n/2.
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __restrict__ G,
                                                       int rows) {
   extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
       min(rows, N - r0) * N, [&](int e) { return g[(size_t)r0 * N + e]; },
       [&](int e, float2 v) { buf[e] = v; });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
+  block_fft<LOGN>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const float in = 1.f / (float)p.n;
   for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
 }
 
 // g holds slabs g_l0 .. (all of them, or one streamed chunk).
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
                                                       void* __restrict__ g, int slab0, int cols,
                                                       int g_l0) {
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
         buf[c * N + k2] = v;
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
+  block_fft<LOGN>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int l = slab0 + blockIdx.y;
   for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
@@ -698,7 +698,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   }
 }
 
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
   extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
         if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
+  block_fft<LOGN>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   float2* gg = G + (size_t)blockIdx.y * N * N;
   for (int e = threadIdx.x; e < cols * N; e += NTF) {
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
   }
 }
 
-template <bool WIDE>
+template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __restrict__ G,
                                                       int rows) {
   extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
         buf[b * N + ((ix - p.n / 2) & (N - 1))] = v;
       });
   __syncthreads();
-  block_fft<WIDE>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
+  block_fft<LOGN>(buf, p.log2_grid, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
   for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e >> p.log2_grid;
@@ -1027,9 +1027,11 @@ __global__ __launch_bounds__(256) void k_absmax_final(float* __restrict__ dyn, i
 // ================================================================ drivers
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
-// The instantiation of an FFT kernel for transforms of N points (the wide
-// passes only where N exceeds LDS_CPLX).
-#define FFT_KERNEL(k, N) ((N) > LDS_CPLX ? k<true> : k<false>)
+// The instantiation of an FFT kernel for transforms of N points: a fixed
+// size from 256 to 8192 points (8192: the wide passes), else the run-time one.
+#define FFT_KERNEL(k, N)                                                                  \
+  ((N) == 512 ? k<9> : (N) == 256 ? k<8> : (N) == 1024 ? k<10> : (N) == 2048 ? k<11>   \
+   : (N) == 4096 ? k<12> : (N) == 8192 ? k<13> : k<0>)
 
 // Sets the float16 input factor of a call from its input (x != NULL) or from
 // a known bound alone.

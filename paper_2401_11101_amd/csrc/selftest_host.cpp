@@ -100,7 +100,9 @@ static int check_candidates() {
       const int half_m = wp / 2 - 1;
       for (int it = 0; it < 40; ++it) {
         const int l = (int)(U(rng) * (hp / 2));
-        const double th = U(rng) * 2 * M_PI;
+        // the first angles lie next to pi/2 (tiny |cos|: the widest margins)
+        static const double near[8] = {0.0, 1e-7, -3e-6, 8e-6, -2e-5, 1e-4, -7e-4, 3e-3};
+        const double th = it < 8 ? M_PI / 2 + near[it] : U(rng) * 2 * M_PI;
         const float2 cs = make_float2((float)std::cos(th), (float)std::sin(th));
         const float gcl = gs * (float)l;
         std::vector<int> owners(2 * half_m + 1, 0);
@@ -110,9 +112,9 @@ static int check_candidates() {
             for (int sx = -1; sx <= 1; ++sx) {
               int mlo = 1, mhi = 0, olo = 1, ohi = 0;
               tile_candidates(ncw, gcl, cs, (float)(X0 + sx * grid) - M, (float)(Y0 + sy * grid) - M,
-                              (float)(tile + 2 * M), (float)(tile + 2 * M), half_m, mlo, mhi);
-              tile_candidates(ncw, gcl, cs, (float)(X0 + sx * grid) - 1.f, (float)(Y0 + sy * grid) - 1.f,
-                              (float)(tile + 2), (float)(tile + 2), half_m, olo, ohi);
+                              (float)(tile + 2 * M - 1), (float)(tile + 2 * M - 1), half_m, mlo, mhi);
+              tile_candidates(ncw, gcl, cs, (float)(X0 + sx * grid), (float)(Y0 + sy * grid),
+                              (float)tile, (float)tile, half_m, olo, ohi);
               for (int m = -half_m; m <= half_m; ++m) {
                 float X, Y;
                 sample_pos(ncw, gcl, cs, m, X, Y);
