@@ -500,7 +500,7 @@ def admm_tv_reconstruction(dev, outer=4, inner=4):
             "tv_kernels": krep}
 
 
-def table1(dev, sizes=(256, 512, 1024, 2048)):
+def table1(dev, sizes=(256, 512, 1024, 1536, 2048)):
     """The paper's timing-table workload: N projections of N x N, 8-bit data,
     tilt 20 deg, N^3 volume (float32).  Fourier-route FBP (fp32 and fp16
     storage) against the direct line-integral FBP, device-resident, one timed
@@ -553,6 +553,85 @@ def table1(dev, sizes=(256, 512, 1024, 2048)):
             "rows": rows, "end_to_end_N1024_f16": e2e,
             "paper_context": "A100 40 GB, times including the chunked host-device pipeline: Fourier "
                              "3.0 / 8.6 / 21.1 s and direct 9.3 / 52.1 / 222.1 s at N = 1024 / 1536 / 2048"}
+
+
+def _u8_projections(N, tilt, dev, chunk=8):
+    """8-bit ellipsoid projections of the N-cube workload, generated a few
+    angles at a time (the float32 set of N = 3072 alone would take 116 GB)."""
+    ells = synth.random_ellipsoids(20, N, N, seed=0)
+    theta = synth.angles(N)
+    probe = synth.project_ellipsoids(ells, 32, N, N, tilt, theta=theta[::max(1, N // 32)][:32], device=dev,
+                                     dtype=torch.float32, theta_chunk=chunk)
+    scale = 255.0 / (1.1 * float(probe.max()))
+    del probe
+    d8 = torch.empty((N, N, N), dtype=torch.uint8, device=dev)
+    for t0 in range(0, N, chunk):
+        t1 = min(N, t0 + chunk)
+        d = synth.project_ellipsoids(ells, t1 - t0, N, N, tilt, theta=theta[t0:t1], device=dev,
+                                     dtype=torch.float32, theta_chunk=chunk)
+        d8[t0:t1] = torch.clamp(d * scale, 0, 255).round().to(torch.uint8)
+        if t0 % (64 * chunk) == 0:
+            log(f"  projections {t1} / {N}")
+    return d8
+
+
+def table1_3072(dev):
+    """The N = 3072 row of the timing table: 3072 projections of 3072 x 3072,
+    8-bit data, tilt 20 deg, 3072^3 float32 volume (116 GB).  fp16 storage;
+    the detector is padded to the next power of two (4096, pad factor 1.33)
+    instead of 2x (8192, whose spectra alone would take 412 GB); the slab
+    planes live in pinned host memory when the device cannot hold them beside
+    the volume, the data and the spectra.  One timed run each of the Fourier
+    and the direct FBP, data and volume resident on the device."""
+    from paper_2401_11101_amd import Plan
+
+    N = 3072
+    tilt = np.deg2rad(20.0)
+    torch.cuda.empty_cache()
+    torch._C._host_emptyCache()  # pinned blocks cached from earlier rows
+    # the plan first: its device workspace takes what the volume and the data
+    # leave, and its pinned host buffer may be refused by the host
+    budget = torch.cuda.mem_get_info()[0] - 5 * N ** 3 - (10 << 30)
+    log(f"table1: N = 3072 (plan, {budget / 2**30:.0f} GiB of device memory for the workspace)")
+    try:
+        plan = Plan(N, N, N, N, N, tilt, data_dtype="u8", storage_dtype="f16", pad_u=1.0, pad_v=1.0,
+                    hbm_budget=budget)
+    except (RuntimeError, torch.cuda.OutOfMemoryError) as e:
+        torch.cuda.empty_cache()
+        return {"N": N, "not_run": f"plan allocation failed: {str(e).splitlines()[0]}",
+                "device_budget_gib": round(budget / 2**30, 1)}
+    i = plan.info
+    log("table1: N = 3072 (data)")
+    d8 = _u8_projections(N, tilt, dev)
+    vol = torch.empty((N, N, N), dtype=torch.float32, device=dev)
+    row = {"N": N, "pad": [1.0, 1.0], "w_p": i.w_p, "h_p": i.h_p, "grid": i.grid,
+           "fourier_f16_layout": (f"spectra {'host' if i.spill_spectra else 'device'}, slab planes "
+                                  f"{'host' if i.spill_slabs else 'device'} ({i.host_bytes / 2**30:.1f} GiB "
+                                  f"pinned host memory), device workspace {i.work_bytes / 2**30:.1f} GiB")}
+    log("table1: N = 3072 (Fourier FBP)")
+    plan.fbp(d8, out=vol)  # warm-up: binds the host buffer, uploads the tables
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.fbp(d8, out=vol)
+    torch.cuda.synchronize()
+    row["fourier_f16_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    row["fourier_f16_gvoxel_per_s"] = round(N ** 3 / (row["fourier_f16_ms"] * 1e-3) / 1e9, 4)
+    row["finite"] = bool(torch.isfinite(vol[::256]).all())
+    # the direct FBP uses the plan's tables only: its filtered rows (116 GB)
+    # take the place of the Fourier workspace
+    plan.work = None
+    torch.cuda.empty_cache()
+    log("table1: N = 3072 (direct FBP)")
+    t0 = time.perf_counter()
+    plan.direct_fbp(d8, out=vol)
+    torch.cuda.synchronize()
+    row["direct_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    row["direct_voxel_angles_per_s"] = float(f"{float(N) ** 4 / (row['direct_ms'] * 1e-3):.4g}")
+    row["gain_f16"] = round(row["direct_ms"] / row["fourier_f16_ms"], 3)
+    del plan, vol, d8
+    torch.cuda.empty_cache()
+    row["paper_context"] = "A100 40 GB, including the host pipeline: Fourier 77.7 s, direct 1002.2 s"
+    return row
 
 
 def _end_to_end(plan, d8, vol, stream):
@@ -634,6 +713,8 @@ def main():
                     help="also time the 1024^2 x 512 volume, CGLS and the TV-regularised ADMM")
     ap.add_argument("--admm", action="store_true",
                     help="also time the TV-regularised ADMM and its kernels (part of --extra)")
+    ap.add_argument("--table1-3072", action="store_true",
+                    help="the N = 3072 row of the timing table (fp16, ~2 minutes, 116 GB volume)")
     ap.add_argument("--table1", action="store_true",
                     help="also run the Fourier-vs-direct timing table (N = 256 .. 2048, 8-bit data)")
     ap.add_argument("--search", action="store_true",
@@ -744,6 +825,11 @@ def main():
         line["admm_tv"] = admm_tv_reconstruction(dev)
     if args.table1:
         line["table1"] = table1(dev)
+    if args.table1_3072:
+        try:
+            line["table1_3072"] = table1_3072(dev)
+        except (RuntimeError, torch.cuda.OutOfMemoryError) as e:
+            line["table1_3072"] = {"N": 3072, "not_run": str(e).splitlines()[0]}
     if args.search or args.extra:
         log("timing the axis and tilt sweeps")
         line["search"] = search_sweeps(dev, data)
