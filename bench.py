@@ -781,6 +781,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "dtype_note": ("float32 data, spectra, slab planes and accumulation, FP64 tables; the gridding and "
+                       "x3 products run on the matrix cores as three bf16 products per term (hi hi, hi lo, "
+                       "lo hi of bf16 hi / lo splits, ~2^-17 relative per term)"),
         "data": "synthetic",
         "config": {"workload": "FBP of a 256x256x256 volume from 400 projections over [0, 2pi), "
                                "tilt 25 deg, detector 256x256, 50 ellipsoids + 0.5% noise, Shepp-Logan",
