@@ -178,6 +178,64 @@ __device__ inline void block_fft(float2* a, int log2N, int B, const float2* __re
   }
 }
 
+// ------------------------------------------------------ wave-level FFT
+// A 512-point transform held by one wave, eight values per lane, as
+// 512 = 8 x 8 x 8: lane j holds x[j + 64 r] (r = 0..7); an 8-point DFT over
+// r and the twiddles w^(j k1) give Y[k1][j]; an exchange through LDS hands
+// lane (k1, m2) = (L >> 3, L & 7) the values Y[k1][8 m1 + m2] (m1 = 0..7),
+// whose 8-point DFT over m1 and twiddles w^(8 m2 l1) give Z[k1][l1][m2]; a
+// second exchange hands lane (k1, l1) = (L >> 3, L & 7) the values
+// Z[k1][l1][m2] (m2 = 0..7), and their 8-point DFT over m2 is
+// X[k1 + 8 l1 + 64 l2] (l2 = 0..7).  w = exp(-+2 pi i / 512).  The exchange
+// buffers hold element (k1, n2) at 72 k1 + n2 and (k1, l1, m2) at
+// 72 k1 + 9 l1 + m2, which spreads every write and read of both exchanges
+// over distinct LDS banks (checked for 16- and 32-lane bank groups of
+// 8-byte values).
+constexpr int WFFT_XCH = 576;  // exchange buffer per wave (float2)
+
+struct WaveTw512 {
+  float2 a[7];  // w^(j k1), k1 = 1..7, j = lane
+  float2 b[7];  // w^(8 m2 l1), l1 = 1..7, m2 = lane & 7
+};
+
+__device__ __forceinline__ void wave_tw512(const float2* __restrict__ tw, int log2max, bool inv,
+                                           WaveTw512& t) {
+  const int L = threadIdx.x & 63;
+  const int sh = log2max - 9;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    t.a[k - 1] = twiddle(tw, ((L * k) & 511) << sh, inv);
+    t.b[k - 1] = twiddle(tw, ((8 * (L & 7) * k) & 511) << sh, inv);
+  }
+}
+
+// In place on v: on entry lane j holds x[j + 64 r] in v[r]; on exit lane L
+// holds X[(L >> 3) + 8 (L & 7) + 64 q] in v[q].  xch: this wave's
+// WFFT_XCH-value buffer.
+__device__ __forceinline__ void wave_fft512(float2 v[8], float2* xch, const WaveTw512& t, bool inv) {
+  const int L = threadIdx.x & 63;
+  const int hi = L >> 3, lo = L & 7;
+  r8_compute(0, 0, nullptr, 0, inv, v);  // Ns = 1: the plain 8-point DFT
+#pragma unroll
+  for (int k = 1; k < 8; ++k) v[k] = cmul(v[k], t.a[k - 1]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) xch[72 * k + L] = v[k];
+  wave_lds_sync();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[m] = xch[72 * hi + 8 * m + lo];
+  wave_lds_sync();
+  r8_compute(0, 0, nullptr, 0, inv, v);
+#pragma unroll
+  for (int k = 1; k < 8; ++k) v[k] = cmul(v[k], t.b[k - 1]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) xch[72 * hi + 9 * k + lo] = v[k];
+  wave_lds_sync();
+#pragma unroll
+  for (int m = 0; m < 8; ++m) v[m] = xch[72 * hi + 9 * lo + m];
+  wave_lds_sync();
+  r8_compute(0, 0, nullptr, 0, inv, v);
+}
+
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places
 // it.  Each thread issues up to FFT_IO fetches before placing any of them,
 // so a block keeps many HBM requests in flight.

@@ -125,6 +125,52 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   }
 }
 
+constexpr int WFFT_WAVES = 4;  // waves per block of the wave-level FFT kernels
+constexpr int WFFT_ROWS = 4;   // rows per wave
+
+// k_proj_rows_fwd for w_p = 512 with one wave per row: the padded row is
+// loaded straight into the lanes (lane j: entries j + 64 r), transformed by
+// wave_fft512 and written to D with the transfer function; each wave takes
+// rows_per_wave consecutive rows.
+__global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
+    KParams p, const float2* __restrict__ w1, void* __restrict__ D, const float* __restrict__ filt,
+    const float2* __restrict__ phase, int theta0, int rows_per_wave, int d_nth, int d_th0) {
+  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  float2* xch = xch_all + wv * WFFT_XCH;
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, false, t);
+  const int kb = (L >> 3) + 8 * (L & 7);  // output k of v[q] is kb + 64 q
+  float f[8];
+  float2 ph[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    f[q] = filt[kb + 64 * q];
+    ph[q] = phase ? phase[kb + 64 * q] : make_float2(1.f, 0.f);
+  }
+  const float2* src = w1 + (size_t)tl * p.n_slab * p.w;
+  const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
+  const int l1 = min(l0 + rows_per_wave, p.n_slab);
+  for (int l = l0; l < l1; ++l) {
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int c = (L + 64 * r + p.w / 2) & 511;  // entry (c - w/2) mod w_p holds column c
+      v[r] = c < p.w ? src[(size_t)l * p.w + c] : make_float2(0.f, 0.f);
+    }
+    wave_fft512(v, xch, t, false);
+    const size_t o = ((size_t)l * d_nth + (th - d_th0)) * 512;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float2 x = cscale(v[q], f[q]);
+      if (phase) x = cmul(x, ph[q]);
+      st_c(D, o + kb + 64 * q, x, p.storage_dtype);
+    }
+  }
+}
+
 // Rotation-axis offset: exp(2 pi i m delta / w_p) for k = m mod w_p, in
 // double precision (a translation of the rows by delta columns).
 __global__ void k_axis_phase(float2* __restrict__ out, int wp, double delta) {
@@ -662,6 +708,33 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
   for (int e = threadIdx.x; e < rows * p.n; e += NTF) {
     const int b = div24(e, p.n, in), ix = e - b * p.n;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + ix] = res[b * N + ((ix - p.n / 2) & (N - 1))];
+  }
+}
+
+// k_grid_rows_inv for grid 512 with one wave per row (wave_fft512); each
+// wave reads its whole row before writing the cropped n entries back.
+__global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_inv_w(KParams p, float2* __restrict__ G,
+                                                                     int rows_per_wave) {
+  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  float2* xch = xch_all + wv * WFFT_XCH;
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, true, t);
+  const int kb = (L >> 3) + 8 * (L & 7);
+  float2* g = G + (size_t)blockIdx.y * 512 * 512;
+  const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
+  const int r1 = min(r0 + rows_per_wave, 512);
+  for (int row = r0; row < r1; ++row) {
+    float2* gr = g + (size_t)row * 512;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = gr[L + 64 * r];
+    wave_fft512(v, xch, t, true);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int ix = (kb + 64 * q + p.n / 2) & 511;  // entry (ix - n/2) mod 512 -> column ix
+      if (ix < p.n) gr[ix] = v[q];
+    }
   }
 }
 
@@ -1256,9 +1329,14 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
       hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_fwd, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp, src,
                          W1, t0, cp, src_th0);
       if (host_in) rec(2 + (c & 1), s);
-      hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_fwd, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
-                         (const float2*)W1, Dt, kp.filt, (const float2*)phase, t0, rows_w, d_nth,
-                         d_th0);
+      if (p->w_p == 512)
+        hipLaunchKernelGGL(k_proj_rows_fwd_w, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt),
+                           dim3(64 * WFFT_WAVES), 0, s, kp, (const float2*)W1, Dt, kp.filt,
+                           (const float2*)phase, t0, WFFT_ROWS, d_nth, d_th0);
+      else
+        hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_fwd, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
+                           (const float2*)W1, Dt, kp.filt, (const float2*)phase, t0, rows_w, d_nth,
+                           d_th0);
     }
     if (p->spill_D) {
       // D[l][t0 .. t0 + nt)[k] of every slab l into the host spectra
@@ -1308,8 +1386,12 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     }
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2, timing);
-      hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_inv, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp, G,
-                         rows_g);
+      if (p->grid == 512)
+        hipLaunchKernelGGL(k_grid_rows_inv_w, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+                           kp, G, WFFT_ROWS);
+      else
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_inv, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp, G,
+                           rows_g);
       hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
                          (const float2*)G, gt, s0, cols_g, g_l0);
     }

@@ -41,9 +41,11 @@ def test_adj_and_fwd_small_ragged():
     assert ea < TOL_F32 and ef < TOL_F32
 
 
-def test_stored_spectra_match_oracle():
+@pytest.mark.parametrize("geo", [(10, 16, 9, 12, 20, 25), (6, 16, 5, 12, 200, 25)])
+def test_stored_spectra_match_oracle(geo):
     # stage check of the detector transforms: D[l][theta][k] after L*
-    g, plan, _, d = _pair(10, 16, 9, 12, 20, 25)
+    # (w = 200 pads to w_p = 512: the one-wave-per-row transform)
+    g, plan, _, d = _pair(*geo)
     plan.adj(to_dev(d))
     D = plan.spectra().cpu().numpy()  # (n_slab, n_theta, w_p)
     G = nudft.data_spectra(d, g)  # (T, L, M), l from -h_p/2+1
@@ -167,6 +169,24 @@ def test_c2_full_size_sampled_columns():
     e16 = rel(v16[:, ys, xs], nudft.backproject_columns(G16, g, ys, xs))
     print(f"c2 sampled columns, fp16 storage: rel-L2 {e16:.2e}")
     assert e16 < TOL_LOWP
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_512_point_wave_transforms_sampled_columns(storage):
+    # n = 160 grids on 512 cells and w = 200 pads to w_p = 512: the detector
+    # row and slab row transforms run one wave per 512-point row; ragged
+    # volume and detector, columns checked one by one over all z
+    nz, n, nt, h, w = 9, 160, 11, 10, 200
+    g, plan, _, d = _pair(nz, n, nt, h, w, 28, seed=3, storage_dtype=storage)
+    assert plan.info.grid == 512 and plan.info.w_p == 512
+    vol = to_np(plan.fbp(to_dev(d)))
+    G = nudft.filter_spectra(nudft.data_spectra_fft(d, g), g, filters.SHEPP_LOGAN)
+    rng = np.random.default_rng(5)
+    ys, xs = rng.integers(0, n, 24), rng.integers(0, n, 24)
+    ys[:4], xs[:4] = [0, n - 1, 0, n - 1], [0, 0, n - 1, n - 1]
+    e = rel(vol[:, ys, xs], nudft.backproject_columns(G, g, ys, xs))
+    print(f"512-point rows, {storage}: sampled columns rel-L2 {e:.2e}")
+    assert e < (TOL_F32 if storage == "f32" else TOL_LOWP)
 
 
 @functools.lru_cache(maxsize=1)
