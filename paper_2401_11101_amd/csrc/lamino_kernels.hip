@@ -31,6 +31,13 @@ namespace lam {
 constexpr int NT = 256;        // threads per block (x3 transform, interpolation)
 constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 
+constexpr int WFFT_WAVES = 4;  // waves per block of the wave-level row FFT kernels
+constexpr int WFFT_ROWS = 4;   // rows per wave
+// columns per block of the wave-level column FFT kernels: detector columns
+// (real input, measured faster at 8) and slab columns (measured faster at 16)
+constexpr int WFFT_CW_DET = 8;
+constexpr int WFFT_CW_SLAB = 16;
+
 // ====================================================== detector transforms
 // W1 layout: [theta_local][n_slab][w] float2.
 
@@ -87,6 +94,77 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   }
 }
 
+// k_proj_cols_fwd for h_p = 512 with one wave per complex column: a block
+// stages CW column pairs of one projection (2 CW input columns, contiguous
+// rows) into LDS, column-major with stride WCOL_S(CW) so that the staging
+// stores and every access of the transform fall in distinct banks; each wave
+// transforms CW / 8 columns in place (the column's own LDS span is its
+// exchange buffer), writes the spectrum back in natural order, and the
+// block then separates the two real spectra of each pair and writes rows
+// l = 0 .. n_slab-1 of W1, 2 CW consecutive columns per row.
+constexpr __host__ __device__ int wcol_stride(int cw) { return WFFT_XCH + 32 / cw; }
+
+template <int CW>
+__global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* __restrict__ data,
+                                                         float2* __restrict__ w1, int theta0,
+                                                         int data_th0) {
+  constexpr int S = wcol_stride(CW);
+  __shared__ float2 buf[CW * S];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int c0 = blockIdx.x * 2 * CW;
+  float* bf = reinterpret_cast<float*>(buf);
+  const size_t row0 = (size_t)(th - data_th0) * p.h;
+  const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
+  stage_in<float>(
+      p.h * 2 * CW,
+      [&](int e) {
+        const int r = e / (2 * CW), c = c0 + e % (2 * CW);
+        if (c >= p.w) return 0.f;
+        float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
+        if (p.dark) {
+          const size_t q = (size_t)r * p.w + c;
+          v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
+        }
+        return v * fin;
+      },
+      [&](int e, float v) {
+        const int r = e / (2 * CW), cl = e % (2 * CW);
+        bf[2 * ((cl >> 1) * S + ((r - p.h / 2) & 511)) + (cl & 1)] = v;
+      });
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, false, t);
+  __syncthreads();
+  const int kb = (L >> 3) + 8 * (L & 7);
+#pragma unroll
+  for (int cc = 0; cc < CW / 8; ++cc) {
+    float2* col = buf + (wv * (CW / 8) + cc) * S;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int pos = L + 64 * r;  // entry (row - h/2) mod 512 holds detector row `row`
+      v[r] = ((pos + p.h / 2) & 511) < p.h ? col[pos] : make_float2(0.f, 0.f);
+    }
+    wave_fft512(v, col, t, false);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+  }
+  __syncthreads();
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  for (int e = threadIdx.x; e < p.n_slab * 2 * CW; e += 512) {
+    const int l = e / (2 * CW), cl = e % (2 * CW);
+    const int c = c0 + cl;
+    if (c >= p.w) continue;
+    const float2* z = buf + (cl >> 1) * S;
+    const float2 zl = z[l], zm = cconj(z[(512 - l) & 511]);
+    float2 x;
+    if ((cl & 1) == 0) x = cscale(cadd(zl, zm), 0.5f);        // (Z[l] + conj Z[-l]) / 2
+    else x = cscale(mul_mi(csub(zl, zm)), 0.5f);              // (Z[l] - conj Z[-l]) / 2i
+    w1[base + (size_t)l * p.w + c] = x;
+  }
+}
+
 // Rows l of the column spectra: w_p-point FFT along u, times the transfer
 // function, stored as D[l][theta - d_th0][k] (k = m mod w_p) with d_nth
 // projections per slab (all of them, or one streamed chunk).
@@ -125,8 +203,6 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   }
 }
 
-constexpr int WFFT_WAVES = 4;  // waves per block of the wave-level FFT kernels
-constexpr int WFFT_ROWS = 4;   // rows per wave
 
 // k_proj_rows_fwd for w_p = 512 with one wave per row: the padded row is
 // loaded straight into the lanes (lane j: entries j + 64 r), transformed by
@@ -771,6 +847,55 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   }
 }
 
+// k_grid_cols_adj for grid 512 with one wave per column: a block stages CW
+// columns of the row-transformed slab (rows of CW consecutive entries) into
+// LDS column-major with stride wcol_stride(CW), each wave transforms CW / 8
+// of them in place and writes the cropped column back, and the block writes
+// rows y of the slab plane, CW consecutive columns per row, with the psi
+// correction.
+template <int CW>
+__global__ __launch_bounds__(512) void k_grid_cols_adj_w(KParams p, const float2* __restrict__ G,
+                                                         void* __restrict__ g, int slab0, int g_l0) {
+  constexpr int S = wcol_stride(CW);
+  __shared__ float2 buf[CW * S];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int ix0 = blockIdx.x * CW;
+  const float2* gg = G + (size_t)blockIdx.y * 512 * 512;
+  stage_in<float2>(
+      512 * CW,
+      [&](int e) {
+        const int k2 = e / CW, c = e % CW;
+        return (ix0 + c < p.n) ? gg[(size_t)k2 * 512 + ix0 + c] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) { buf[(e % CW) * S + e / CW] = v; });
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, true, t);
+  __syncthreads();
+  const int kb = (L >> 3) + 8 * (L & 7);
+#pragma unroll
+  for (int cc = 0; cc < CW / 8; ++cc) {
+    float2* col = buf + (wv * (CW / 8) + cc) * S;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = col[L + 64 * r];
+    wave_fft512(v, col, t, true);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int y = (kb + 64 * q + p.n / 2) & 511;  // entry (y - n/2) mod 512 -> row y
+      if (y < p.n) col[y] = v[q];
+    }
+  }
+  __syncthreads();
+  const int l = slab0 + blockIdx.y;
+  for (int e = threadIdx.x; e < p.n * CW; e += 512) {
+    const int y = e / CW, c = e % CW;
+    const int ix = ix0 + c;
+    if (ix >= p.n) continue;
+    const float2 v = cscale(buf[c * S + y], p.deapod[ix] * p.deapod[y]);
+    st_c(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix, v, p.storage_dtype);
+  }
+}
+
 template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
@@ -1326,8 +1451,12 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     }
     {
       StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2, timing);
-      hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_fwd, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp, src,
-                         W1, t0, cp, src_th0);
+      if (p->h_p == 512)
+        hipLaunchKernelGGL(k_proj_cols_fwd_w<WFFT_CW_DET>, dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp, src,
+                           W1, t0, src_th0);
+      else
+        hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_fwd, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp, src,
+                           W1, t0, cp, src_th0);
       if (host_in) rec(2 + (c & 1), s);
       if (p->w_p == 512)
         hipLaunchKernelGGL(k_proj_rows_fwd_w, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt),
@@ -1392,8 +1521,12 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
       else
         hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_inv, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp, G,
                            rows_g);
-      hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
-                         (const float2*)G, gt, s0, cols_g, g_l0);
+      if (p->grid == 512)
+        hipLaunchKernelGGL(k_grid_cols_adj_w<WFFT_CW_SLAB>, dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
+                           (const float2*)G, gt, s0, g_l0);
+      else
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
+                           (const float2*)G, gt, s0, cols_g, g_l0);
     }
     if (p->spill_g) {
       rec(4 + (j & 1), s);

@@ -171,14 +171,15 @@ def test_c2_full_size_sampled_columns():
     assert e16 < TOL_LOWP
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_512_point_wave_transforms_sampled_columns(storage):
-    # n = 160 grids on 512 cells and w = 200 pads to w_p = 512: the detector
-    # row and slab row transforms run one wave per 512-point row; ragged
-    # volume and detector, columns checked one by one over all z
-    nz, n, nt, h, w = 9, 160, 11, 10, 200
+@pytest.mark.parametrize("storage,h", [("f32", 10), ("f16", 10), ("f32", 150), ("bf16", 150)])
+def test_512_point_wave_transforms_sampled_columns(storage, h):
+    # n = 160 grids on 512 cells, w = 200 pads to w_p = 512 and h = 150 to
+    # h_p = 512: the detector and slab transforms of 512 points run one wave
+    # per row or column; ragged volume and detector, columns checked one by
+    # one over all z
+    nz, n, nt, w = 9, 160, 11, 200
     g, plan, _, d = _pair(nz, n, nt, h, w, 28, seed=3, storage_dtype=storage)
-    assert plan.info.grid == 512 and plan.info.w_p == 512
+    assert plan.info.grid == 512 and plan.info.w_p == 512 and plan.info.h_p == (512 if h == 150 else 32)
     vol = to_np(plan.fbp(to_dev(d)))
     G = nudft.filter_spectra(nudft.data_spectra_fft(d, g), g, filters.SHEPP_LOGAN)
     rng = np.random.default_rng(5)
