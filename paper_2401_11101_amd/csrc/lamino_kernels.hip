@@ -347,6 +347,98 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   }
 }
 
+// k_proj_rows_inv for w_p = 512 with one wave per row (wave_fft512).
+__global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, const void* __restrict__ D,
+                                                                     float2* __restrict__ w1, int theta0,
+                                                                     int rows_per_wave) {
+  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  float2* xch = xch_all + wv * WFFT_XCH;
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, true, t);
+  const int kb = (L >> 3) + 8 * (L & 7);
+  float2* dst = w1 + (size_t)tl * p.n_slab * p.w;
+  const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
+  const int l1 = min(l0 + rows_per_wave, p.n_slab);
+  for (int l = l0; l < l1; ++l) {
+    const size_t o = ((size_t)l * p.n_theta + th) * 512;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)  // the Nyquist bin (k = 256) is not part of the sum
+      v[r] = (r == 4 && L == 0) ? make_float2(0.f, 0.f) : ld_c(D, o + L + 64 * r, p.storage_dtype);
+    wave_fft512(v, xch, t, true);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = (kb + 64 * q + p.w / 2) & 511;  // entry (c - w/2) mod w_p -> column c
+      if (c < p.w) dst[(size_t)l * p.w + c] = v[q];
+    }
+  }
+}
+
+// k_proj_cols_inv for h_p = 512 with one wave per complex column: the half
+// spectra of CW column pairs are completed by Hermitian symmetry into LDS
+// columns (stride wcol_stride(CW); the Nyquist entry is zeroed on loading),
+// transformed in place by one wave each, and written as 2 CW detector
+// columns per row.
+template <int CW>
+__global__ __launch_bounds__(512) void k_proj_cols_inv_w(KParams p, const float2* __restrict__ w1,
+                                                         void* __restrict__ data, int theta0, float scale) {
+  constexpr int S = wcol_stride(CW);
+  __shared__ float2 buf[CW * S];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int tl = blockIdx.y;
+  const int th = theta0 + tl;
+  const int c0 = blockIdx.x * 2 * CW;
+  const size_t base = (size_t)tl * p.n_slab * p.w;
+  stage_in<float4>(
+      p.n_slab * CW,
+      [&](int e) {
+        const int l = e / CW, pp = e % CW;
+        const int ca = c0 + 2 * pp, cb = ca + 1;
+        const float2 xa = ca < p.w ? w1[base + (size_t)l * p.w + ca] : make_float2(0.f, 0.f);
+        const float2 xb = cb < p.w ? w1[base + (size_t)l * p.w + cb] : make_float2(0.f, 0.f);
+        return make_float4(xa.x, xa.y, xb.x, xb.y);
+      },
+      [&](int e, float4 x) {
+        const int l = e / CW, pp = e % CW;
+        float2* z = buf + pp * S;
+        // x = (Re X_a, Im X_a, Re X_b, Im X_b)
+        if (l == 0) {
+          z[0] = make_float2(x.x, x.z);
+        } else {
+          z[l] = make_float2(x.x - x.w, x.y + x.z);
+          z[512 - l] = make_float2(x.x + x.w, x.z - x.y);
+        }
+      });
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, true, t);
+  __syncthreads();
+  const int kb = (L >> 3) + 8 * (L & 7);
+#pragma unroll
+  for (int cc = 0; cc < CW / 8; ++cc) {
+    float2* col = buf + (wv * (CW / 8) + cc) * S;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = (r == 4 && L == 0) ? make_float2(0.f, 0.f) : col[L + 64 * r];
+    wave_fft512(v, col, t, true);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+  }
+  __syncthreads();
+  const float* bf = reinterpret_cast<const float*>(buf);
+  const float out = scale * (p.dyn ? p.dyn[1] : 1.f);
+  for (int e = threadIdx.x; e < p.h * 2 * CW; e += 512) {
+    const int r = e / (2 * CW), cl = e % (2 * CW);
+    const int c = c0 + cl;
+    if (c >= p.w) continue;
+    const int pos = (r - p.h / 2) & 511;
+    st_r(data, ((size_t)th * p.h + r) * p.w + c, bf[2 * ((cl >> 1) * S + pos) + (cl & 1)] * out,
+         p.data_dtype);
+  }
+}
+
 // ================================================================ gridding
 // Gaussian weights exp(-beta d^2) at the 2M taps d = (1 - M) - f, ..., M - f
 // by the recurrence w_{i+1} = w_i r_i, r_{i+1} = r_i exp(-2 beta).
@@ -954,6 +1046,82 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
   for (int e = threadIdx.x; e < rows * N; e += NTF) {
     const int b = e >> p.log2_grid;
     if (r0 + b < N) g[(size_t)(r0 + b) * N + (e & (N - 1))] = res[e];
+  }
+}
+
+// k_grid_cols_fwd for grid 512 with one wave per column: CW columns of the
+// slab plane (psi-corrected) are placed at rows (y - n/2) mod 512 of LDS
+// columns, transformed in place (entries that hold no row are zeroed on
+// loading), and written as rows k2 of CW consecutive grid columns.
+template <int CW>
+__global__ __launch_bounds__(512) void k_grid_cols_fwd_w(KParams p, const void* __restrict__ g,
+                                                         float2* __restrict__ G, int slab0) {
+  constexpr int S = wcol_stride(CW);
+  __shared__ float2 buf[CW * S];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  const int ix0 = blockIdx.x * CW;
+  const int l = slab0 + blockIdx.y;
+  stage_in<float2>(
+      p.n * CW,
+      [&](int e) {
+        const int y = e / CW, ix = ix0 + e % CW;
+        return ix < p.n ? ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype) : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int y = e / CW, c = e % CW;
+        const int ix = ix0 + c;
+        buf[c * S + ((y - p.n / 2) & 511)] = ix < p.n ? cscale(v, p.deapod[ix] * p.deapod[y]) : v;
+      });
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, false, t);
+  __syncthreads();
+  const int kb = (L >> 3) + 8 * (L & 7);
+#pragma unroll
+  for (int cc = 0; cc < CW / 8; ++cc) {
+    float2* col = buf + (wv * (CW / 8) + cc) * S;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int pos = L + 64 * r;  // entry (y - n/2) mod 512 holds row y
+      v[r] = ((pos + p.n / 2) & 511) < p.n ? col[pos] : make_float2(0.f, 0.f);
+    }
+    wave_fft512(v, col, t, false);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+  }
+  __syncthreads();
+  float2* gg = G + (size_t)blockIdx.y * 512 * 512;
+  for (int e = threadIdx.x; e < 512 * CW; e += 512) {
+    const int k2 = e / CW, c = e % CW;
+    if (ix0 + c < p.n) gg[(size_t)k2 * 512 + ix0 + c] = buf[c * S + k2];
+  }
+}
+
+// k_grid_rows_fwd for grid 512 with one wave per row: the row's n entries
+// are loaded at (ix - n/2) mod 512 (zero elsewhere), transformed, and the
+// whole row is written back.
+__global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, float2* __restrict__ G,
+                                                                     int rows_per_wave) {
+  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
+  float2* xch = xch_all + wv * WFFT_XCH;
+  WaveTw512 t;
+  wave_tw512(p.tw, p.log2_twmax, false, t);
+  const int kb = (L >> 3) + 8 * (L & 7);
+  float2* g = G + (size_t)blockIdx.y * 512 * 512;
+  const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
+  const int r1 = min(r0 + rows_per_wave, 512);
+  for (int row = r0; row < r1; ++row) {
+    float2* gr = g + (size_t)row * 512;
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int ix = (L + 64 * r + p.n / 2) & 511;  // entry (ix - n/2) mod 512 holds column ix
+      v[r] = ix < p.n ? gr[ix] : make_float2(0.f, 0.f);
+    }
+    wave_fft512(v, xch, t, false);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) gr[kb + 64 * q] = v[q];
   }
 }
 
@@ -1631,10 +1799,17 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
-      hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
-                         (const void*)g, G, s0, cols_g);
-      hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_fwd, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp,
-                         G, rows_g);
+      if (p->grid == 512) {
+        hipLaunchKernelGGL(k_grid_cols_fwd_w<WFFT_CW_SLAB>, dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
+                           (const void*)g, G, s0);
+        hipLaunchKernelGGL(k_grid_rows_fwd_w, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+                           kp, G, WFFT_ROWS);
+      } else {
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
+                           (const void*)g, G, s0, cols_g);
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_fwd, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp,
+                           G, rows_g);
+      }
     }
     StageTimer timer(p, s, LAMINO_STAGE_GRIDDING, 1);
     interp_dispatch(kp, G, D, s0, ns, s);
@@ -1646,10 +1821,18 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   for (int t0 = 0; t0 < p->n_theta; t0 += p->theta_chunk) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
-    hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_inv, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
-                       (const void*)D, W1, t0, rows_w);
-    hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_inv, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp,
-                       (const float2*)W1, d_data, t0, cp, scale);
+    if (p->w_p == 512)
+      hipLaunchKernelGGL(k_proj_rows_inv_w, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt), dim3(64 * WFFT_WAVES),
+                         0, s, kp, (const void*)D, W1, t0, WFFT_ROWS);
+    else
+      hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_inv, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
+                         (const void*)D, W1, t0, rows_w);
+    if (p->h_p == 512)
+      hipLaunchKernelGGL(k_proj_cols_inv_w<WFFT_CW_DET>, dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
+                         (const float2*)W1, d_data, t0, scale);
+    else
+      hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_inv, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp,
+                         (const float2*)W1, d_data, t0, cp, scale);
   }
   return hipGetLastError();
 }
