@@ -1257,6 +1257,96 @@ __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void*
     }
 }
 
+// The same product with each slab-plane value read once: a wave owns 32
+// columns and X3B_ZT 32-row z tiles (accumulators for 256 slices), the
+// block's four waves take neighbouring column tiles, and the phase-table
+// fragments of the block's rows are staged once per K step in LDS (double
+// buffered; the next step's fragments are fetched from HBM while the
+// current step's products run).  blockIdx.y selects 256-slice row blocks.
+constexpr int X3B_WAVES = 4;
+constexpr int X3B_ZT = 8;
+constexpr int X3B_ROWS = 32 * X3B_ZT;  // slices per block
+
+template <int PREC>
+__global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_x3_adj_b(KParams p, const void* __restrict__ g,
+                                                             int g_ld, float* __restrict__ vol,
+                                                             int v_ld, int col0, int ncol, int z0,
+                                                             int nzc, int out_z0) {
+  // [buffer][hi, lo][row * 2 + half]: the fragments of one K step
+  __shared__ v8u sa[2][2][X3B_ROWS * 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 31, h = lane >> 5;
+  const int col = (blockIdx.x * X3B_WAVES + wave) * 32 + r;
+  const int zb = blockIdx.y * X3B_ROWS;
+  const float outs = p.x3_out_scale * (p.dyn ? p.dyn[1] : 1.f);
+  const int K = p.x3a_k;
+  const bool cok = col < ncol;
+  const size_t cidx = cok ? col : 0;
+  // this thread's share of a step's fragments: 4 of the 2 x 512
+  v8u an[4];
+  auto fetch_a = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + 64 * X3B_WAVES * u;
+      const int hl = i >> 9, f = i & 511;
+      const int row = min(z0 + zb + (f >> 1), p.x3a_rows - 1);
+      const size_t o = (((size_t)st * p.x3a_rows + row) * 2 + (f & 1)) * 8 + (hl ? (size_t)p.x3a_rows * K : 0);
+      an[u] = *reinterpret_cast<const v8u*>(p.x3a + o);
+    }
+  };
+  auto store_a = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + 64 * X3B_WAVES * u;
+      sa[buf][i >> 9][i & 511] = an[u];
+    }
+  };
+  v16f acc[X3B_ZT] = {};
+  X3AdjB<PREC> bc, bn;
+  x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, 0, h, bc);
+  fetch_a(0);
+  store_a(0);
+  const int ns = K >> 4;
+  for (int st = 0; st < ns; ++st) {
+    __syncthreads();  // step st's fragments are in LDS; step st - 1's buffer is free
+    const int nx = min(st + 1, ns - 1);  // the last step refetches itself
+    x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, nx << 4, h, bn);
+    fetch_a(nx);
+    v8u bh, bl;
+    if constexpr (PREC == 0) {
+      float x[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        x[2 * q] = bc.v[q].x;
+        x[2 * q + 1] = bc.v[q].y;
+      }
+      split8(x, bh, bl);
+    } else {
+      // 16-bit complex pairs (re | im << 16) are the operand's pairs of k
+      bh = __builtin_bit_cast(v8u, make_uint4(bc.v[0], bc.v[1], bc.v[2], bc.v[3]));
+    }
+    const v8u* ah = sa[st & 1][0];
+    const v8u* al = sa[st & 1][1];
+#pragma unroll
+    for (int i = 0; i < X3B_ZT; ++i) {
+      const int f = (32 * i + r) * 2 + h;
+      acc[i] = mfma16<PREC>(ah[f], bh, acc[i]);
+      acc[i] = mfma16<PREC>(al[f], bh, acc[i]);
+      if constexpr (PREC == 0) acc[i] = mfma16<0>(ah[f], bl, acc[i]);
+    }
+    if (st + 1 < ns) store_a((st + 1) & 1);
+    bc = bn;
+  }
+  if (!cok) return;
+#pragma unroll
+  for (int i = 0; i < X3B_ZT; ++i)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int z = zb + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * v_ld + col0 + col] = acc[i][v] * outs;
+    }
+}
+
 // ghat[l][col] = sum_z exp(-2 pi i x3 l cos(phi) / h_p) f[z][col]
 __global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float* __restrict__ f,
                                                           void* __restrict__ g) {
@@ -1501,13 +1591,13 @@ static inline char* wptr(const lamino_plan_s* p, size_t off) {
 // vol rows of v_ld columns.
 static void launch_x3_adj(const KParams& kp, const void* g, int g_ld, float* vol, int v_ld,
                           int vcol0, int ncol, int z0, int nzc, int out_z0, hipStream_t s) {
-  const dim3 grid(cdiv(ncol, 32), cdiv(nzc, X3_ROWS));
+  const dim3 grid(cdiv(ncol, 32 * X3B_WAVES), cdiv(nzc, X3B_ROWS));
   if (kp.storage_dtype == LAMINO_F32)
-    hipLaunchKernelGGL(k_x3_adj<0>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(k_x3_adj_b<0>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
   else if (kp.storage_dtype == LAMINO_F16)
-    hipLaunchKernelGGL(k_x3_adj<1>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(k_x3_adj_b<1>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
   else
-    hipLaunchKernelGGL(k_x3_adj<2>, grid, dim3(64 * X3_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(k_x3_adj_b<2>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
 }
 
 // Backprojection pipeline.  Device-resident plans with device data and
