@@ -1131,15 +1131,11 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, 
 //   adj: vol[z][col] = sum_k A[z][k] B[k][col], k = 2l + c,
 //        B[2l][col] = Re g[l][col], B[2l + 1][col] = Im g[l][col];
 //   fwd: G[2l + c][col] = sum_z A[2l + c][z] f[z][col] gives Re / Im ghat.
-// A wave computes X3_ZT row tiles of 32 x 32 (v_mfma_f32_32x32x16) that
-// share one column tile, so each B fragment is loaded and split once; four
-// waves per block along the rows.  Lane l holds A[l % 32][8 (l / 32) + t],
-// B[8 (l / 32) + t][l % 32] and C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].
-// Float32 operands are split into bf16 hi + lo (three products); float16 /
-// bfloat16 slab data are exact in their own format (two products).
-constexpr int X3_WAVES = 4;
-constexpr int X3_ZT = 2;
-constexpr int X3_ROWS = 32 * X3_ZT * X3_WAVES;  // rows per block
+// Lane l of a 32 x 32 x 16 product (v_mfma_f32_32x32x16) holds
+// A[l % 32][8 (l / 32) + t], B[8 (l / 32) + t][l % 32] and
+// C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32].  Float32 operands are split into
+// bf16 hi + lo (three products); float16 / bfloat16 slab data are exact in
+// their own format (two products).
 
 __device__ __forceinline__ void split8(const float x[8], v8u& hi, v8u& lo) {
   typedef unsigned v4u __attribute__((ext_vector_type(4)));
@@ -1152,14 +1148,6 @@ __device__ __forceinline__ void split8(const float x[8], v8u& hi, v8u& lo) {
   }
   hi = __builtin_bit_cast(v8u, h4);
   lo = __builtin_bit_cast(v8u, l4);
-}
-
-// A fragment of tile row `row` (clamped into the table) at K-step s
-__device__ __forceinline__ void load_afrag(const unsigned short* tab, int rows, int K, int row,
-                                           int h, int s, v8u& hi, v8u& lo) {
-  const size_t o = (((size_t)s * rows + row) * 2 + h) * 8;
-  hi = *reinterpret_cast<const v8u*>(tab + o);
-  lo = *reinterpret_cast<const v8u*>(tab + (size_t)rows * K + o);
 }
 
 // Raw B operand of K-step k0 for the adjoint: this lane's slabs
@@ -1191,73 +1179,8 @@ __device__ __forceinline__ void x3_adj_loadb(const KParams& p, const void* g, in
 }
 
 // vol[z0 - out_z0 + z][col0 + col] for z in [0, nzc) and the ncol columns
-// col of g (slab stride g_ld columns); vol rows have v_ld columns.  The
-// operands of K-step k0 + 16 are loaded while the products of step k0 run.
-template <int PREC>
-__global__ __launch_bounds__(64 * X3_WAVES) void k_x3_adj(KParams p, const void* __restrict__ g,
-                                                          int g_ld, float* __restrict__ vol,
-                                                          int v_ld, int col0, int ncol, int z0,
-                                                          int nzc, int out_z0) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = lane & 31, h = lane >> 5;
-  const int col = blockIdx.x * 32 + r;
-  const int zt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;
-  if (zt >= nzc) return;
-  const float outs = p.x3_out_scale * (p.dyn ? p.dyn[1] : 1.f);
-  const int K = p.x3a_k;
-  int arow[X3_ZT];
-#pragma unroll
-  for (int i = 0; i < X3_ZT; ++i) arow[i] = min(z0 + zt + 32 * i + r, p.x3a_rows - 1);
-  const bool cok = col < ncol;
-  const size_t cidx = cok ? col : 0;
-  v16f acc[X3_ZT] = {};
-  X3AdjB<PREC> bc, bn;
-  v8u ahc[X3_ZT], alc[X3_ZT], ahn[X3_ZT], aln[X3_ZT];
-  x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, 0, h, bc);
-#pragma unroll
-  for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, 0, ahc[i], alc[i]);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const int kn = min(k0 + 16, K - 16);  // the last step reloads itself
-    x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, kn, h, bn);
-#pragma unroll
-    for (int i = 0; i < X3_ZT; ++i) load_afrag(p.x3a, p.x3a_rows, K, arow[i], h, kn >> 4, ahn[i], aln[i]);
-    v8u bh, bl;
-    if constexpr (PREC == 0) {
-      float x[8];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        x[2 * q] = bc.v[q].x;
-        x[2 * q + 1] = bc.v[q].y;
-      }
-      split8(x, bh, bl);
-    } else {
-      // 16-bit complex pairs (re | im << 16) are the operand's pairs of k
-      bh = __builtin_bit_cast(v8u, make_uint4(bc.v[0], bc.v[1], bc.v[2], bc.v[3]));
-    }
-#pragma unroll
-    for (int i = 0; i < X3_ZT; ++i) {
-      acc[i] = mfma16<PREC>(ahc[i], bh, acc[i]);
-      acc[i] = mfma16<PREC>(alc[i], bh, acc[i]);
-      if constexpr (PREC == 0) acc[i] = mfma16<0>(ahc[i], bl, acc[i]);
-    }
-    bc = bn;
-#pragma unroll
-    for (int i = 0; i < X3_ZT; ++i) {
-      ahc[i] = ahn[i];
-      alc[i] = aln[i];
-    }
-  }
-  if (!cok) return;
-#pragma unroll
-  for (int i = 0; i < X3_ZT; ++i)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int z = zt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
-      if (z < nzc) vol[(size_t)(z0 - out_z0 + z) * v_ld + col0 + col] = acc[i][v] * outs;
-    }
-}
-
-// The same product with each slab-plane value read once: a wave owns 32
+// col of g (slab stride g_ld columns); vol rows have v_ld columns.  Each
+// slab-plane value is read once: a wave owns 32
 // columns and X3B_ZT 32-row z tiles (accumulators for 256 slices), the
 // block's four waves take neighbouring column tiles, and the phase-table
 // fragments of the block's rows are staged once per K step in LDS (double
@@ -1347,49 +1270,82 @@ __global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
-// ghat[l][col] = sum_z exp(-2 pi i x3 l cos(phi) / h_p) f[z][col]
-__global__ __launch_bounds__(64 * X3_WAVES) void k_x3_fwd(KParams p, const float* __restrict__ f,
-                                                          void* __restrict__ g) {
+
+// ghat[l][col] = sum_z exp(-2 pi i x3 l cos(phi) / h_p) f[z][col], each
+// volume value read once per 256 rows: a wave owns 32 columns and X3B_ZT
+// 32-row tiles of the 2 n_slab rows, the block's waves take neighbouring
+// column tiles, and the phase fragments of the block's rows are staged per
+// K step in double-buffered LDS (as in k_x3_adj_b).
+__global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_x3_fwd_b(
+    KParams p, const float* __restrict__ f, void* __restrict__ g) {
+  __shared__ v8u sa[2][2][X3B_ROWS * 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int ncol = p.n * p.n;
-  const int col = blockIdx.x * 32 + r;
-  const int mt = blockIdx.y * X3_ROWS + wave * 32 * X3_ZT;  // rows 2l + c
-  if (mt >= 2 * p.n_slab) return;
+  const int col = (blockIdx.x * X3B_WAVES + wave) * 32 + r;
+  const int mb = blockIdx.y * X3B_ROWS;  // rows 2l + c
   const int K = p.x3f_k;
-  int arow[X3_ZT];
-#pragma unroll
-  for (int i = 0; i < X3_ZT; ++i) arow[i] = min(mt + 32 * i + r, p.x3f_rows - 1);
   const bool cok = col < ncol;
   const size_t cidx = cok ? col : 0;
-  v16f acc[X3_ZT] = {};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    float x[8];
+  v8u an[4];
+  auto fetch_a = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + 64 * X3B_WAVES * u;
+      const int hl = i >> 9, fr = i & 511;
+      const int row = min(mb + (fr >> 1), p.x3f_rows - 1);
+      const size_t o = (((size_t)st * p.x3f_rows + row) * 2 + (fr & 1)) * 8 + (hl ? (size_t)p.x3f_rows * K : 0);
+      an[u] = *reinterpret_cast<const v8u*>(p.x3f + o);
+    }
+  };
+  auto store_a = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = threadIdx.x + 64 * X3B_WAVES * u;
+      sa[buf][i >> 9][i & 511] = an[u];
+    }
+  };
+  auto load_b = [&](int st, float x[8]) {
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-      const int z = k0 + 8 * h + t;
-      x[t] = (cok && z < p.nz) ? f[(size_t)z * ncol + cidx] : 0.f;
+      const int z = 16 * st + 8 * h + t;
+      x[t] = f[(size_t)min(z, p.nz - 1) * ncol + cidx];
+      if (!cok || z >= p.nz) x[t] = 0.f;
     }
+  };
+  v16f acc[X3B_ZT] = {};
+  float xc[8], xn[8];
+  load_b(0, xc);
+  fetch_a(0);
+  store_a(0);
+  const int ns = K >> 4;
+  for (int st = 0; st < ns; ++st) {
+    __syncthreads();
+    const int nx = min(st + 1, ns - 1);
+    load_b(nx, xn);
+    fetch_a(nx);
     v8u bh, bl;
-    split8(x, bh, bl);
+    split8(xc, bh, bl);
+    const v8u* ah = sa[st & 1][0];
+    const v8u* al = sa[st & 1][1];
 #pragma unroll
-    for (int i = 0; i < X3_ZT; ++i) {
-      v8u ah, al;
-      load_afrag(p.x3f, p.x3f_rows, K, arow[i], h, k0 >> 4, ah, al);
-      acc[i] = mfma16<0>(ah, bh, acc[i]);
-      acc[i] = mfma16<0>(ah, bl, acc[i]);
-      acc[i] = mfma16<0>(al, bh, acc[i]);
+    for (int i = 0; i < X3B_ZT; ++i) {
+      const int fr = (32 * i + r) * 2 + h;
+      acc[i] = mfma16<0>(ah[fr], bh, acc[i]);
+      acc[i] = mfma16<0>(ah[fr], bl, acc[i]);
+      acc[i] = mfma16<0>(al[fr], bh, acc[i]);
     }
+    if (st + 1 < ns) store_a((st + 1) & 1);
+#pragma unroll
+    for (int t = 0; t < 8; ++t) xc[t] = xn[t];
   }
   if (!cok) return;
-  // float16 storage: the call's input factor and the planes' static factor
   const float gs = p.fwd_g_scale * (p.dyn ? p.dyn[0] : 1.f);
-  // rows 2l (re) and 2l + 1 (im) sit in accumulators v and v + 1 (v % 4 = 0, 2)
 #pragma unroll
-  for (int i = 0; i < X3_ZT; ++i)
+  for (int i = 0; i < X3B_ZT; ++i)
 #pragma unroll
     for (int v = 0; v < 16; v += 2) {
-      const int m = mt + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
+      const int m = mb + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
       const int l = m >> 1;
       if (l < p.n_slab)
         st_c(g, (size_t)l * ncol + col, make_float2(acc[i][v] * gs, acc[i][v + 1] * gs),
@@ -1877,8 +1833,8 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
   if (kp.dyn) input_factor(kp, d_vol, (size_t)p->nz * ncol, LAMINO_F32, 0.f, s);
   {
     StageTimer timer(p, s, LAMINO_STAGE_X3, 1);
-    hipLaunchKernelGGL(k_x3_fwd, dim3(cdiv(ncol, 32), cdiv(2 * p->n_slab, X3_ROWS)),
-                       dim3(64 * X3_WAVES), 0, s, kp, d_vol, g);
+    hipLaunchKernelGGL(k_x3_fwd_b, dim3(cdiv(ncol, 32 * X3B_WAVES), cdiv(2 * p->n_slab, X3B_ROWS)),
+                       dim3(64 * X3B_WAVES), 0, s, kp, d_vol, g);
   }
   const int rows_g = std::min(fft_capacity(p->grid) / p->grid, p->grid);
   const int cols_g = std::min(fft_capacity(p->grid) / p->grid, p->n);
