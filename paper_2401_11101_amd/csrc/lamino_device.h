@@ -179,61 +179,111 @@ __device__ inline void block_fft(float2* a, int log2N, int B, const float2* __re
 }
 
 // ------------------------------------------------------ wave-level FFT
-// A 512-point transform held by one wave, eight values per lane, as
-// 512 = 8 x 8 x 8: lane j holds x[j + 64 r] (r = 0..7); an 8-point DFT over
-// r and the twiddles w^(j k1) give Y[k1][j]; an exchange through LDS hands
-// lane (k1, m2) = (L >> 3, L & 7) the values Y[k1][8 m1 + m2] (m1 = 0..7),
-// whose 8-point DFT over m1 and twiddles w^(8 m2 l1) give Z[k1][l1][m2]; a
-// second exchange hands lane (k1, l1) = (L >> 3, L & 7) the values
-// Z[k1][l1][m2] (m2 = 0..7), and their 8-point DFT over m2 is
-// X[k1 + 8 l1 + 64 l2] (l2 = 0..7).  w = exp(-+2 pi i / 512).  The exchange
-// buffers hold element (k1, n2) at 72 k1 + n2 and (k1, l1, m2) at
-// 72 k1 + 9 l1 + m2, which spreads every write and read of both exchanges
-// over distinct LDS banks (checked for 16- and 32-lane bank groups of
-// 8-byte values).
-constexpr int WFFT_XCH = 576;  // exchange buffer per wave (float2)
+// A transform of N = 64 R points (R = 8 or 16) held by one wave, R values
+// per lane: lane j holds x[j + 64 r] (r < R).  With n = 64 n1 + n2 and
+// k = k1 + R k2, an R-point DFT over n1 = r and the twiddles w^(j k1) give
+// Y[k1][j] (w = exp(-+2 pi i / N)); the 64-point DFTs over n2 = 8 m1 + m2
+// follow as 8 x 8: an exchange through LDS hands lane (k, m2) =
+// (L >> 3, L & 7) the values Y[k1][8 m1 + m2] (m1 = 0..7) of k1 = k + 8 i
+// (i < R / 8), whose 8-point DFTs over m1 and twiddles w64^(m2 l1) give
+// Z[k1][l1][m2]; a second exchange hands lane (k, l1) = (L >> 3, L & 7) the
+// values Z[k1][l1][m2] (m2 = 0..7), and their 8-point DFTs over m2 are
+// X[k1 + R l1 + 8 R l2] (l2 = 0..7).  The exchange buffers hold element
+// (k1, n2) at 72 k1 + n2 and (k1, l1, m2) at 72 k1 + 9 l1 + m2, which
+// spreads every write and read of both exchanges over distinct LDS banks
+// (checked for 16- and 32-lane bank groups of 8-byte values).
+__host__ __device__ constexpr int wfft_xch(int R) { return 72 * R; }  // exchange buffer (float2)
 
-struct WaveTw512 {
-  float2 a[7];  // w^(j k1), k1 = 1..7, j = lane
-  float2 b[7];  // w^(8 m2 l1), l1 = 1..7, m2 = lane & 7
+template <int R>
+struct WaveTw {
+  float2 a[R - 1];  // w^(j k1), k1 = 1 .. R-1, j = lane
+  float2 b[7];      // w64^(m2 l1), l1 = 1 .. 7, m2 = lane & 7
 };
 
-__device__ __forceinline__ void wave_tw512(const float2* __restrict__ tw, int log2max, bool inv,
-                                           WaveTw512& t) {
+template <int R>
+__device__ __forceinline__ void wave_tw(const float2* __restrict__ tw, int log2max, bool inv,
+                                        WaveTw<R>& t) {
+  constexpr int N = 64 * R;
+  constexpr int LOGN = R == 8 ? 9 : 10;
   const int L = threadIdx.x & 63;
-  const int sh = log2max - 9;
 #pragma unroll
-  for (int k = 1; k < 8; ++k) {
-    t.a[k - 1] = twiddle(tw, ((L * k) & 511) << sh, inv);
-    t.b[k - 1] = twiddle(tw, ((8 * (L & 7) * k) & 511) << sh, inv);
+  for (int k = 1; k < R; ++k) t.a[k - 1] = twiddle(tw, ((L * k) & (N - 1)) << (log2max - LOGN), inv);
+#pragma unroll
+  for (int k = 1; k < 8; ++k) t.b[k - 1] = twiddle(tw, (((L & 7) * k) & 63) << (log2max - 6), inv);
+}
+
+// R-point DFT in registers, natural order in and out (R = 8 or 16: two
+// 8-point DFTs of the even and odd inputs combined with w16^k)
+template <int R>
+__device__ __forceinline__ void dft_reg(float2 v[R], bool inv) {
+  if constexpr (R == 8) {
+    r8_compute(0, 0, nullptr, 0, inv, v);  // Ns = 1: the plain 8-point DFT
+  } else {
+    float2 e[8], o[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      e[r] = v[2 * r];
+      o[r] = v[2 * r + 1];
+    }
+    r8_compute(0, 0, nullptr, 0, inv, e);
+    r8_compute(0, 0, nullptr, 0, inv, o);
+    // w16^k = cos(k pi / 8) -+ i sin(k pi / 8)
+    const float c[8] = {1.f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                        0.f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
+    const float sk[8] = {0.f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+                         1.f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float cs = c[k], sn = inv ? sk[k] : -sk[k];
+      const float2 t = make_float2(o[k].x * cs - o[k].y * sn, o[k].x * sn + o[k].y * cs);
+      v[k] = cadd(e[k], t);
+      v[k + 8] = csub(e[k], t);
+    }
   }
 }
 
+// Output register q of lane L holds X[wave_out<R>(L, q)].
+template <int R>
+__device__ __forceinline__ int wave_out(int L, int q) {
+  return (L >> 3) + 8 * (q >> 3) + R * (L & 7) + 8 * R * (q & 7);
+}
+
 // In place on v: on entry lane j holds x[j + 64 r] in v[r]; on exit lane L
-// holds X[(L >> 3) + 8 (L & 7) + 64 q] in v[q].  xch: this wave's
-// WFFT_XCH-value buffer.
-__device__ __forceinline__ void wave_fft512(float2 v[8], float2* xch, const WaveTw512& t, bool inv) {
+// holds X[wave_out<R>(L, q)] in v[q].  xch: this wave's wfft_xch(R)-value
+// buffer.
+template <int R>
+__device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<R>& t, bool inv) {
   const int L = threadIdx.x & 63;
   const int hi = L >> 3, lo = L & 7;
-  r8_compute(0, 0, nullptr, 0, inv, v);  // Ns = 1: the plain 8-point DFT
+  dft_reg<R>(v, inv);
 #pragma unroll
-  for (int k = 1; k < 8; ++k) v[k] = cmul(v[k], t.a[k - 1]);
+  for (int k = 1; k < R; ++k) v[k] = cmul(v[k], t.a[k - 1]);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) xch[72 * k + L] = v[k];
+  for (int k = 0; k < R; ++k) xch[72 * k + L] = v[k];
   wave_lds_sync();
 #pragma unroll
-  for (int m = 0; m < 8; ++m) v[m] = xch[72 * hi + 8 * m + lo];
-  wave_lds_sync();
-  r8_compute(0, 0, nullptr, 0, inv, v);
+  for (int i = 0; i < R / 8; ++i)
 #pragma unroll
-  for (int k = 1; k < 8; ++k) v[k] = cmul(v[k], t.b[k - 1]);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) xch[72 * hi + 9 * k + lo] = v[k];
+    for (int m = 0; m < 8; ++m) v[8 * i + m] = xch[72 * (hi + 8 * i) + 8 * m + lo];
   wave_lds_sync();
 #pragma unroll
-  for (int m = 0; m < 8; ++m) v[m] = xch[72 * hi + 9 * lo + m];
+  for (int i = 0; i < R / 8; ++i) {
+    r8_compute(0, 0, nullptr, 0, inv, v + 8 * i);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) v[8 * i + k] = cmul(v[8 * i + k], t.b[k - 1]);
+  }
+#pragma unroll
+  for (int i = 0; i < R / 8; ++i)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) xch[72 * (hi + 8 * i) + 9 * k + lo] = v[8 * i + k];
   wave_lds_sync();
-  r8_compute(0, 0, nullptr, 0, inv, v);
+#pragma unroll
+  for (int i = 0; i < R / 8; ++i)
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[8 * i + m] = xch[72 * (hi + 8 * i) + 9 * lo + m];
+  wave_lds_sync();
+#pragma unroll
+  for (int i = 0; i < R / 8; ++i) r8_compute(0, 0, nullptr, 0, inv, v + 8 * i);
 }
 
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places

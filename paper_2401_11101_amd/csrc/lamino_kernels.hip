@@ -34,9 +34,12 @@ constexpr int TILE_MAX = 64;   // largest interpolation tile edge
 constexpr int WFFT_WAVES = 4;  // waves per block of the wave-level row FFT kernels
 constexpr int WFFT_ROWS = 4;   // rows per wave
 // columns per block of the wave-level column FFT kernels: detector columns
-// (real input, measured faster at 8) and slab columns (measured faster at 16)
+// (real input, measured faster at 8) and slab columns of 512 points
+// (measured faster at 16); 1024-point slab columns take 8 (16 would need
+// 148 KB of LDS per block)
 constexpr int WFFT_CW_DET = 8;
 constexpr int WFFT_CW_SLAB = 16;
+constexpr int WFFT_CW_WIDE = 8;
 
 // ====================================================== detector transforms
 // W1 layout: [theta_local][n_slab][w] float2.
@@ -94,21 +97,22 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   }
 }
 
-// k_proj_cols_fwd for h_p = 512 with one wave per complex column: a block
+// k_proj_cols_fwd for h_p = N = 64 R (512 or 1024) with one wave per complex column: a block
 // stages CW column pairs of one projection (2 CW input columns, contiguous
-// rows) into LDS, column-major with stride WCOL_S(CW) so that the staging
+// rows) into LDS, column-major with stride wcol_stride(R, CW) so that the staging
 // stores and every access of the transform fall in distinct banks; each wave
 // transforms CW / 8 columns in place (the column's own LDS span is its
 // exchange buffer), writes the spectrum back in natural order, and the
 // block then separates the two real spectra of each pair and writes rows
 // l = 0 .. n_slab-1 of W1, 2 CW consecutive columns per row.
-constexpr __host__ __device__ int wcol_stride(int cw) { return WFFT_XCH + 32 / cw; }
+constexpr __host__ __device__ int wcol_stride(int R, int cw) { return wfft_xch(R) + 32 / cw; }
 
-template <int CW>
+template <int R, int CW>
 __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* __restrict__ data,
                                                          float2* __restrict__ w1, int theta0,
                                                          int data_th0) {
-  constexpr int S = wcol_stride(CW);
+  constexpr int N = 64 * R;
+  constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int tl = blockIdx.y;
@@ -131,24 +135,23 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
       },
       [&](int e, float v) {
         const int r = e / (2 * CW), cl = e % (2 * CW);
-        bf[2 * ((cl >> 1) * S + ((r - p.h / 2) & 511)) + (cl & 1)] = v;
+        bf[2 * ((cl >> 1) * S + ((r - p.h / 2) & (N - 1))) + (cl & 1)] = v;
       });
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, false, t);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, false, t);
   __syncthreads();
-  const int kb = (L >> 3) + 8 * (L & 7);
 #pragma unroll
   for (int cc = 0; cc < CW / 8; ++cc) {
     float2* col = buf + (wv * (CW / 8) + cc) * S;
-    float2 v[8];
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int pos = L + 64 * r;  // entry (row - h/2) mod 512 holds detector row `row`
-      v[r] = ((pos + p.h / 2) & 511) < p.h ? col[pos] : make_float2(0.f, 0.f);
+    for (int r = 0; r < R; ++r) {
+      const int pos = L + 64 * r;  // entry (row - h/2) mod N holds detector row `row`
+      v[r] = ((pos + p.h / 2) & (N - 1)) < p.h ? col[pos] : make_float2(0.f, 0.f);
     }
-    wave_fft512(v, col, t, false);
+    wave_fft<R>(v, col, t, false);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+    for (int q = 0; q < R; ++q) col[wave_out<R>(L, q)] = v[q];
   }
   __syncthreads();
   const size_t base = (size_t)tl * p.n_slab * p.w;
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
     const int c = c0 + cl;
     if (c >= p.w) continue;
     const float2* z = buf + (cl >> 1) * S;
-    const float2 zl = z[l], zm = cconj(z[(512 - l) & 511]);
+    const float2 zl = z[l], zm = cconj(z[(N - l) & (N - 1)]);
     float2 x;
     if ((cl & 1) == 0) x = cscale(cadd(zl, zm), 0.5f);        // (Z[l] + conj Z[-l]) / 2
     else x = cscale(mul_mi(csub(zl, zm)), 0.5f);              // (Z[l] - conj Z[-l]) / 2i
@@ -204,45 +207,42 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
 }
 
 
-// k_proj_rows_fwd for w_p = 512 with one wave per row: the padded row is
+// k_proj_rows_fwd for w_p = N = 64 R (512 or 1024) with one wave per row: the padded row is
 // loaded straight into the lanes (lane j: entries j + 64 r), transformed by
-// wave_fft512 and written to D with the transfer function; each wave takes
+// wave_fft and written to D with the transfer function; each wave takes
 // rows_per_wave consecutive rows.
+template <int R>
 __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
     KParams p, const float2* __restrict__ w1, void* __restrict__ D, const float* __restrict__ filt,
     const float2* __restrict__ phase, int theta0, int rows_per_wave, int d_nth, int d_th0) {
-  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  constexpr int N = 64 * R;
+  __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  float2* xch = xch_all + wv * WFFT_XCH;
+  float2* xch = xch_all + wv * wfft_xch(R);
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, false, t);
-  const int kb = (L >> 3) + 8 * (L & 7);  // output k of v[q] is kb + 64 q
-  float f[8];
-  float2 ph[8];
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, false, t);
+  float f[R];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    f[q] = filt[kb + 64 * q];
-    ph[q] = phase ? phase[kb + 64 * q] : make_float2(1.f, 0.f);
-  }
+  for (int q = 0; q < R; ++q) f[q] = filt[wave_out<R>(L, q)];
   const float2* src = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
   for (int l = l0; l < l1; ++l) {
-    float2 v[8];
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int c = (L + 64 * r + p.w / 2) & 511;  // entry (c - w/2) mod w_p holds column c
+    for (int r = 0; r < R; ++r) {
+      const int c = (L + 64 * r + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p holds column c
       v[r] = c < p.w ? src[(size_t)l * p.w + c] : make_float2(0.f, 0.f);
     }
-    wave_fft512(v, xch, t, false);
-    const size_t o = ((size_t)l * d_nth + (th - d_th0)) * 512;
+    wave_fft<R>(v, xch, t, false);
+    const size_t o = ((size_t)l * d_nth + (th - d_th0)) * N;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < R; ++q) {
       float2 x = cscale(v[q], f[q]);
-      if (phase) x = cmul(x, ph[q]);
-      st_c(D, o + kb + 64 * q, x, p.storage_dtype);
+      if (phase) x = cmul(x, phase[wave_out<R>(L, q)]);
+      st_c(D, o + wave_out<R>(L, q), x, p.storage_dtype);
     }
   }
 }
@@ -347,45 +347,47 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_inv(KParams p, const float2* 
   }
 }
 
-// k_proj_rows_inv for w_p = 512 with one wave per row (wave_fft512).
+// k_proj_rows_inv for w_p = N = 64 R (512 or 1024) with one wave per row (wave_fft).
+template <int R>
 __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, const void* __restrict__ D,
                                                                      float2* __restrict__ w1, int theta0,
                                                                      int rows_per_wave) {
-  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  constexpr int N = 64 * R;
+  __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  float2* xch = xch_all + wv * WFFT_XCH;
+  float2* xch = xch_all + wv * wfft_xch(R);
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, true, t);
-  const int kb = (L >> 3) + 8 * (L & 7);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, true, t);
   float2* dst = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
   for (int l = l0; l < l1; ++l) {
-    const size_t o = ((size_t)l * p.n_theta + th) * 512;
-    float2 v[8];
+    const size_t o = ((size_t)l * p.n_theta + th) * N;
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r)  // the Nyquist bin (k = 256) is not part of the sum
-      v[r] = (r == 4 && L == 0) ? make_float2(0.f, 0.f) : ld_c(D, o + L + 64 * r, p.storage_dtype);
-    wave_fft512(v, xch, t, true);
+    for (int r = 0; r < R; ++r)  // the Nyquist bin (k = 256) is not part of the sum
+      v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : ld_c(D, o + L + 64 * r, p.storage_dtype);
+    wave_fft<R>(v, xch, t, true);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int c = (kb + 64 * q + p.w / 2) & 511;  // entry (c - w/2) mod w_p -> column c
+    for (int q = 0; q < R; ++q) {
+      const int c = (wave_out<R>(L, q) + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p -> column c
       if (c < p.w) dst[(size_t)l * p.w + c] = v[q];
     }
   }
 }
 
-// k_proj_cols_inv for h_p = 512 with one wave per complex column: the half
+// k_proj_cols_inv for h_p = N = 64 R (512 or 1024) with one wave per complex column: the half
 // spectra of CW column pairs are completed by Hermitian symmetry into LDS
-// columns (stride wcol_stride(CW); the Nyquist entry is zeroed on loading),
+// columns (stride wcol_stride(R, CW); the Nyquist entry is zeroed on loading),
 // transformed in place by one wave each, and written as 2 CW detector
 // columns per row.
-template <int CW>
+template <int R, int CW>
 __global__ __launch_bounds__(512) void k_proj_cols_inv_w(KParams p, const float2* __restrict__ w1,
                                                          void* __restrict__ data, int theta0, float scale) {
-  constexpr int S = wcol_stride(CW);
+  constexpr int N = 64 * R;
+  constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int tl = blockIdx.y;
@@ -409,22 +411,21 @@ __global__ __launch_bounds__(512) void k_proj_cols_inv_w(KParams p, const float2
           z[0] = make_float2(x.x, x.z);
         } else {
           z[l] = make_float2(x.x - x.w, x.y + x.z);
-          z[512 - l] = make_float2(x.x + x.w, x.z - x.y);
+          z[N - l] = make_float2(x.x + x.w, x.z - x.y);
         }
       });
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, true, t);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, true, t);
   __syncthreads();
-  const int kb = (L >> 3) + 8 * (L & 7);
 #pragma unroll
   for (int cc = 0; cc < CW / 8; ++cc) {
     float2* col = buf + (wv * (CW / 8) + cc) * S;
-    float2 v[8];
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = (r == 4 && L == 0) ? make_float2(0.f, 0.f) : col[L + 64 * r];
-    wave_fft512(v, col, t, true);
+    for (int r = 0; r < R; ++r) v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : col[L + 64 * r];
+    wave_fft<R>(v, col, t, true);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+    for (int q = 0; q < R; ++q) col[wave_out<R>(L, q)] = v[q];
   }
   __syncthreads();
   const float* bf = reinterpret_cast<const float*>(buf);
@@ -433,7 +434,7 @@ __global__ __launch_bounds__(512) void k_proj_cols_inv_w(KParams p, const float2
     const int r = e / (2 * CW), cl = e % (2 * CW);
     const int c = c0 + cl;
     if (c >= p.w) continue;
-    const int pos = (r - p.h / 2) & 511;
+    const int pos = (r - p.h / 2) & (N - 1);
     st_r(data, ((size_t)th * p.h + r) * p.w + c, bf[2 * ((cl >> 1) * S + pos) + (cl & 1)] * out,
          p.data_dtype);
   }
@@ -879,28 +880,29 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_inv(KParams p, float2* __rest
   }
 }
 
-// k_grid_rows_inv for grid 512 with one wave per row (wave_fft512); each
+// k_grid_rows_inv for grid N = 64 R (512 or 1024) with one wave per row (wave_fft); each
 // wave reads its whole row before writing the cropped n entries back.
+template <int R>
 __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_inv_w(KParams p, float2* __restrict__ G,
                                                                      int rows_per_wave) {
-  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  constexpr int N = 64 * R;
+  __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  float2* xch = xch_all + wv * WFFT_XCH;
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, true, t);
-  const int kb = (L >> 3) + 8 * (L & 7);
-  float2* g = G + (size_t)blockIdx.y * 512 * 512;
+  float2* xch = xch_all + wv * wfft_xch(R);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, true, t);
+  float2* g = G + (size_t)blockIdx.y * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
-  const int r1 = min(r0 + rows_per_wave, 512);
+  const int r1 = min(r0 + rows_per_wave, N);
   for (int row = r0; row < r1; ++row) {
-    float2* gr = g + (size_t)row * 512;
-    float2 v[8];
+    float2* gr = g + (size_t)row * N;
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = gr[L + 64 * r];
-    wave_fft512(v, xch, t, true);
+    for (int r = 0; r < R; ++r) v[r] = gr[L + 64 * r];
+    wave_fft<R>(v, xch, t, true);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int ix = (kb + 64 * q + p.n / 2) & 511;  // entry (ix - n/2) mod 512 -> column ix
+    for (int q = 0; q < R; ++q) {
+      const int ix = (wave_out<R>(L, q) + p.n / 2) & (N - 1);  // entry (ix - n/2) mod N -> column ix
       if (ix < p.n) gr[ix] = v[q];
     }
   }
@@ -939,41 +941,41 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   }
 }
 
-// k_grid_cols_adj for grid 512 with one wave per column: a block stages CW
+// k_grid_cols_adj for grid N = 64 R (512 or 1024) with one wave per column: a block stages CW
 // columns of the row-transformed slab (rows of CW consecutive entries) into
-// LDS column-major with stride wcol_stride(CW), each wave transforms CW / 8
+// LDS column-major with stride wcol_stride(R, CW), each wave transforms CW / 8
 // of them in place and writes the cropped column back, and the block writes
 // rows y of the slab plane, CW consecutive columns per row, with the psi
 // correction.
-template <int CW>
+template <int R, int CW>
 __global__ __launch_bounds__(512) void k_grid_cols_adj_w(KParams p, const float2* __restrict__ G,
                                                          void* __restrict__ g, int slab0, int g_l0) {
-  constexpr int S = wcol_stride(CW);
+  constexpr int N = 64 * R;
+  constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int ix0 = blockIdx.x * CW;
-  const float2* gg = G + (size_t)blockIdx.y * 512 * 512;
+  const float2* gg = G + (size_t)blockIdx.y * N * N;
   stage_in<float2>(
-      512 * CW,
+      N * CW,
       [&](int e) {
         const int k2 = e / CW, c = e % CW;
-        return (ix0 + c < p.n) ? gg[(size_t)k2 * 512 + ix0 + c] : make_float2(0.f, 0.f);
+        return (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) { buf[(e % CW) * S + e / CW] = v; });
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, true, t);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, true, t);
   __syncthreads();
-  const int kb = (L >> 3) + 8 * (L & 7);
 #pragma unroll
   for (int cc = 0; cc < CW / 8; ++cc) {
     float2* col = buf + (wv * (CW / 8) + cc) * S;
-    float2 v[8];
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) v[r] = col[L + 64 * r];
-    wave_fft512(v, col, t, true);
+    for (int r = 0; r < R; ++r) v[r] = col[L + 64 * r];
+    wave_fft<R>(v, col, t, true);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int y = (kb + 64 * q + p.n / 2) & 511;  // entry (y - n/2) mod 512 -> row y
+    for (int q = 0; q < R; ++q) {
+      const int y = (wave_out<R>(L, q) + p.n / 2) & (N - 1);  // entry (y - n/2) mod N -> row y
       if (y < p.n) col[y] = v[q];
     }
   }
@@ -1049,14 +1051,15 @@ __global__ __launch_bounds__(NTF) void k_grid_rows_fwd(KParams p, float2* __rest
   }
 }
 
-// k_grid_cols_fwd for grid 512 with one wave per column: CW columns of the
-// slab plane (psi-corrected) are placed at rows (y - n/2) mod 512 of LDS
+// k_grid_cols_fwd for grid N = 64 R (512 or 1024) with one wave per column: CW columns of the
+// slab plane (psi-corrected) are placed at rows (y - n/2) mod N of LDS
 // columns, transformed in place (entries that hold no row are zeroed on
 // loading), and written as rows k2 of CW consecutive grid columns.
-template <int CW>
+template <int R, int CW>
 __global__ __launch_bounds__(512) void k_grid_cols_fwd_w(KParams p, const void* __restrict__ g,
                                                          float2* __restrict__ G, int slab0) {
-  constexpr int S = wcol_stride(CW);
+  constexpr int N = 64 * R;
+  constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int ix0 = blockIdx.x * CW;
@@ -1070,58 +1073,58 @@ __global__ __launch_bounds__(512) void k_grid_cols_fwd_w(KParams p, const void* 
       [&](int e, float2 v) {
         const int y = e / CW, c = e % CW;
         const int ix = ix0 + c;
-        buf[c * S + ((y - p.n / 2) & 511)] = ix < p.n ? cscale(v, p.deapod[ix] * p.deapod[y]) : v;
+        buf[c * S + ((y - p.n / 2) & (N - 1))] = ix < p.n ? cscale(v, p.deapod[ix] * p.deapod[y]) : v;
       });
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, false, t);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, false, t);
   __syncthreads();
-  const int kb = (L >> 3) + 8 * (L & 7);
 #pragma unroll
   for (int cc = 0; cc < CW / 8; ++cc) {
     float2* col = buf + (wv * (CW / 8) + cc) * S;
-    float2 v[8];
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int pos = L + 64 * r;  // entry (y - n/2) mod 512 holds row y
-      v[r] = ((pos + p.n / 2) & 511) < p.n ? col[pos] : make_float2(0.f, 0.f);
+    for (int r = 0; r < R; ++r) {
+      const int pos = L + 64 * r;  // entry (y - n/2) mod N holds row y
+      v[r] = ((pos + p.n / 2) & (N - 1)) < p.n ? col[pos] : make_float2(0.f, 0.f);
     }
-    wave_fft512(v, col, t, false);
+    wave_fft<R>(v, col, t, false);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) col[kb + 64 * q] = v[q];
+    for (int q = 0; q < R; ++q) col[wave_out<R>(L, q)] = v[q];
   }
   __syncthreads();
-  float2* gg = G + (size_t)blockIdx.y * 512 * 512;
-  for (int e = threadIdx.x; e < 512 * CW; e += 512) {
+  float2* gg = G + (size_t)blockIdx.y * N * N;
+  for (int e = threadIdx.x; e < N * CW; e += 512) {
     const int k2 = e / CW, c = e % CW;
-    if (ix0 + c < p.n) gg[(size_t)k2 * 512 + ix0 + c] = buf[c * S + k2];
+    if (ix0 + c < p.n) gg[(size_t)k2 * N + ix0 + c] = buf[c * S + k2];
   }
 }
 
-// k_grid_rows_fwd for grid 512 with one wave per row: the row's n entries
-// are loaded at (ix - n/2) mod 512 (zero elsewhere), transformed, and the
+// k_grid_rows_fwd for grid N = 64 R (512 or 1024) with one wave per row: the row's n entries
+// are loaded at (ix - n/2) mod N (zero elsewhere), transformed, and the
 // whole row is written back.
+template <int R>
 __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, float2* __restrict__ G,
                                                                      int rows_per_wave) {
-  __shared__ float2 xch_all[WFFT_WAVES * WFFT_XCH];
+  constexpr int N = 64 * R;
+  __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  float2* xch = xch_all + wv * WFFT_XCH;
-  WaveTw512 t;
-  wave_tw512(p.tw, p.log2_twmax, false, t);
-  const int kb = (L >> 3) + 8 * (L & 7);
-  float2* g = G + (size_t)blockIdx.y * 512 * 512;
+  float2* xch = xch_all + wv * wfft_xch(R);
+  WaveTw<R> t;
+  wave_tw<R>(p.tw, p.log2_twmax, false, t);
+  float2* g = G + (size_t)blockIdx.y * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
-  const int r1 = min(r0 + rows_per_wave, 512);
+  const int r1 = min(r0 + rows_per_wave, N);
   for (int row = r0; row < r1; ++row) {
-    float2* gr = g + (size_t)row * 512;
-    float2 v[8];
+    float2* gr = g + (size_t)row * N;
+    float2 v[R];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int ix = (L + 64 * r + p.n / 2) & 511;  // entry (ix - n/2) mod 512 holds column ix
+    for (int r = 0; r < R; ++r) {
+      const int ix = (L + 64 * r + p.n / 2) & (N - 1);  // entry (ix - n/2) mod N holds column ix
       v[r] = ix < p.n ? gr[ix] : make_float2(0.f, 0.f);
     }
-    wave_fft512(v, xch, t, false);
+    wave_fft<R>(v, xch, t, false);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) gr[kb + 64 * q] = v[q];
+    for (int q = 0; q < R; ++q) gr[wave_out<R>(L, q)] = v[q];
   }
 }
 
@@ -1666,14 +1669,21 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     {
       StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2, timing);
       if (p->h_p == 512)
-        hipLaunchKernelGGL(k_proj_cols_fwd_w<WFFT_CW_DET>, dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp, src,
-                           W1, t0, src_th0);
+        hipLaunchKernelGGL((k_proj_cols_fwd_w<8, WFFT_CW_DET>), dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
+                           src, W1, t0, src_th0);
+      else if (p->h_p == 1024)
+        hipLaunchKernelGGL((k_proj_cols_fwd_w<16, WFFT_CW_DET>), dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
+                           src, W1, t0, src_th0);
       else
         hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_fwd, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp, src,
                            W1, t0, cp, src_th0);
       if (host_in) rec(2 + (c & 1), s);
       if (p->w_p == 512)
-        hipLaunchKernelGGL(k_proj_rows_fwd_w, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt),
+        hipLaunchKernelGGL(k_proj_rows_fwd_w<8>, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt),
+                           dim3(64 * WFFT_WAVES), 0, s, kp, (const float2*)W1, Dt, kp.filt,
+                           (const float2*)phase, t0, WFFT_ROWS, d_nth, d_th0);
+      else if (p->w_p == 1024)
+        hipLaunchKernelGGL(k_proj_rows_fwd_w<16>, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt),
                            dim3(64 * WFFT_WAVES), 0, s, kp, (const float2*)W1, Dt, kp.filt,
                            (const float2*)phase, t0, WFFT_ROWS, d_nth, d_th0);
       else
@@ -1730,13 +1740,19 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2, timing);
       if (p->grid == 512)
-        hipLaunchKernelGGL(k_grid_rows_inv_w, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+        hipLaunchKernelGGL(k_grid_rows_inv_w<8>, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+                           kp, G, WFFT_ROWS);
+      else if (p->grid == 1024)
+        hipLaunchKernelGGL(k_grid_rows_inv_w<16>, dim3(1024 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
                            kp, G, WFFT_ROWS);
       else
         hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_inv, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp, G,
                            rows_g);
       if (p->grid == 512)
-        hipLaunchKernelGGL(k_grid_cols_adj_w<WFFT_CW_SLAB>, dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
+        hipLaunchKernelGGL((k_grid_cols_adj_w<8, WFFT_CW_SLAB>), dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
+                           (const float2*)G, gt, s0, g_l0);
+      else if (p->grid == 1024)
+        hipLaunchKernelGGL((k_grid_cols_adj_w<16, WFFT_CW_WIDE>), dim3(cdiv(p->n, WFFT_CW_WIDE), ns), dim3(512), 0, s, kp,
                            (const float2*)G, gt, s0, g_l0);
       else
         hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
@@ -1846,9 +1862,14 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
     {
       StageTimer timer(p, s, LAMINO_STAGE_SLAB, 2);
       if (p->grid == 512) {
-        hipLaunchKernelGGL(k_grid_cols_fwd_w<WFFT_CW_SLAB>, dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
+        hipLaunchKernelGGL((k_grid_cols_fwd_w<8, WFFT_CW_SLAB>), dim3(cdiv(p->n, WFFT_CW_SLAB), ns), dim3(512), 0, s, kp,
                            (const void*)g, G, s0);
-        hipLaunchKernelGGL(k_grid_rows_fwd_w, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+        hipLaunchKernelGGL(k_grid_rows_fwd_w<8>, dim3(512 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
+                           kp, G, WFFT_ROWS);
+      } else if (p->grid == 1024) {
+        hipLaunchKernelGGL((k_grid_cols_fwd_w<16, WFFT_CW_WIDE>), dim3(cdiv(p->n, WFFT_CW_WIDE), ns), dim3(512), 0, s, kp,
+                           (const void*)g, G, s0);
+        hipLaunchKernelGGL(k_grid_rows_fwd_w<16>, dim3(1024 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
                            kp, G, WFFT_ROWS);
       } else {
         hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
@@ -1868,13 +1889,19 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     StageTimer timer(p, s, LAMINO_STAGE_DETECTOR, 2);
     if (p->w_p == 512)
-      hipLaunchKernelGGL(k_proj_rows_inv_w, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt), dim3(64 * WFFT_WAVES),
+      hipLaunchKernelGGL(k_proj_rows_inv_w<8>, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt), dim3(64 * WFFT_WAVES),
+                         0, s, kp, (const void*)D, W1, t0, WFFT_ROWS);
+    else if (p->w_p == 1024)
+      hipLaunchKernelGGL(k_proj_rows_inv_w<16>, dim3(cdiv(p->n_slab, WFFT_WAVES * WFFT_ROWS), nt), dim3(64 * WFFT_WAVES),
                          0, s, kp, (const void*)D, W1, t0, WFFT_ROWS);
     else
       hipLaunchKernelGGL(FFT_KERNEL(k_proj_rows_inv, p->w_p), dim3(cdiv(p->n_slab, rows_w), nt), dim3(NTF), lds_w, s, kp,
                          (const void*)D, W1, t0, rows_w);
     if (p->h_p == 512)
-      hipLaunchKernelGGL(k_proj_cols_inv_w<WFFT_CW_DET>, dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
+      hipLaunchKernelGGL((k_proj_cols_inv_w<8, WFFT_CW_DET>), dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
+                         (const float2*)W1, d_data, t0, scale);
+    else if (p->h_p == 1024)
+      hipLaunchKernelGGL((k_proj_cols_inv_w<16, WFFT_CW_DET>), dim3(cdiv(p->w, 2 * WFFT_CW_DET), nt), dim3(512), 0, s, kp,
                          (const float2*)W1, d_data, t0, scale);
     else
       hipLaunchKernelGGL(FFT_KERNEL(k_proj_cols_inv, p->h_p), dim3(cdiv(p->w, 2 * cp), nt), dim3(NTF), lds_h, s, kp,

@@ -190,6 +190,35 @@ def test_512_point_wave_transforms_sampled_columns(storage, h):
     assert e < (TOL_F32 if storage == "f32" else TOL_LOWP)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_1024_point_wave_transforms(storage):
+    # n = 300 grids on 1024 cells and h = w = 200 padded by 4 give
+    # h_p = w_p = 1024: every detector and slab transform runs one wave per
+    # 1024-point row or column (16 values per lane).  The FBP on sampled
+    # columns against the exact sums; L through the adjoint identity with a
+    # data set correlated with L f (the FBP check fixes L*).
+    nz, n, nt, h, w = 4, 300, 6, 200, 200
+    g, plan, f, d = _pair(nz, n, nt, h, w, 28, seed=4, pad_u=4.0, pad_v=4.0, storage_dtype=storage)
+    g.pad_u, g.pad_v = 4.0, 4.0
+    assert (plan.info.grid, plan.info.w_p, plan.info.h_p) == (1024, 1024, 1024)
+    tol = TOL_F32 if storage == "f32" else TOL_LOWP
+    vol = to_np(plan.fbp(to_dev(d)))
+    G = nudft.filter_spectra(nudft.data_spectra_fft(d, g), g, filters.SHEPP_LOGAN)
+    rng = np.random.default_rng(6)
+    ys, xs = rng.integers(0, n, 16), rng.integers(0, n, 16)
+    ys[:2], xs[:2] = [0, n - 1], [n - 1, 0]
+    e = rel(vol[:, ys, xs], nudft.backproject_columns(G, g, ys, xs))
+    F = to_dev(f)
+    Lf = plan.fwd(F)
+    noise = torch.from_numpy(rng.standard_normal(tuple(Lf.shape))).to(Lf.device, torch.float32)
+    dd = Lf + 0.1 * Lf.std() * noise
+    a = float((Lf.double() * dd.double()).sum())
+    b = float((F.double() * plan.adj(dd).double()).sum())
+    ea = abs(a - b) / abs(a)
+    print(f"1024-point transforms, {storage}: sampled columns rel-L2 {e:.2e}, adjoint identity {ea:.2e}")
+    assert e < tol and ea < tol
+
+
 @functools.lru_cache(maxsize=1)
 def _quarter_c3():
     # the large-chunk geometry at 1/4 scale: detector 256 wide x 128 rows,
