@@ -1183,38 +1183,41 @@ __device__ __forceinline__ void x3_adj_loadb(const KParams& p, const void* g, in
 
 // vol[z0 - out_z0 + z][col0 + col] for z in [0, nzc) and the ncol columns
 // col of g (slab stride g_ld columns); vol rows have v_ld columns.  Each
-// slab-plane value is read once: a wave owns 32
-// columns and X3B_ZT 32-row z tiles (accumulators for 256 slices), the
-// block's four waves take neighbouring column tiles, and the phase-table
-// fragments of the block's rows are staged once per K step in LDS (double
-// buffered; the next step's fragments are fetched from HBM while the
-// current step's products run).  blockIdx.y selects 256-slice row blocks.
+// slab-plane value is read once: a wave owns 32 columns and ZT 32-row z
+// tiles (ZT = 8: accumulators for 256 slices; 2 for z chunks of at most 64
+// slices), the block's four waves take neighbouring column tiles, and the
+// phase-table fragments of the block's rows are staged once per K step in
+// LDS (double buffered; the next step's fragments are fetched from HBM
+// while the current step's products run).  blockIdx.y selects row blocks.
 constexpr int X3B_WAVES = 4;
 constexpr int X3B_ZT = 8;
 constexpr int X3B_ROWS = 32 * X3B_ZT;  // slices per block
 
-template <int PREC>
+template <int PREC, int ZT>
 __global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(2))) void k_x3_adj_b(KParams p, const void* __restrict__ g,
                                                              int g_ld, float* __restrict__ vol,
                                                              int v_ld, int col0, int ncol, int z0,
                                                              int nzc, int out_z0) {
   // [buffer][hi, lo][row * 2 + half]: the fragments of one K step
-  __shared__ v8u sa[2][2][X3B_ROWS * 2];
+  constexpr int ROWS = 32 * ZT;  // slices per block
+  __shared__ v8u sa[2][2][ROWS * 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 31, h = lane >> 5;
   const int col = (blockIdx.x * X3B_WAVES + wave) * 32 + r;
-  const int zb = blockIdx.y * X3B_ROWS;
+  const int zb = blockIdx.y * ROWS;
   const float outs = p.x3_out_scale * (p.dyn ? p.dyn[1] : 1.f);
   const int K = p.x3a_k;
   const bool cok = col < ncol;
   const size_t cidx = cok ? col : 0;
   // this thread's share of a step's fragments: 4 of the 2 x 512
-  v8u an[4];
+  // this thread's share of a step's fragments: 2 x 2 ROWS of them
+  constexpr int NA = (4 * ROWS) / (64 * X3B_WAVES);
+  v8u an[NA];
   auto fetch_a = [&](int st) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NA; ++u) {
       const int i = threadIdx.x + 64 * X3B_WAVES * u;
-      const int hl = i >> 9, f = i & 511;
+      const int hl = i / (2 * ROWS), f = i % (2 * ROWS);
       const int row = min(z0 + zb + (f >> 1), p.x3a_rows - 1);
       const size_t o = (((size_t)st * p.x3a_rows + row) * 2 + (f & 1)) * 8 + (hl ? (size_t)p.x3a_rows * K : 0);
       an[u] = *reinterpret_cast<const v8u*>(p.x3a + o);
@@ -1222,12 +1225,12 @@ __global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(
   };
   auto store_a = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NA; ++u) {
       const int i = threadIdx.x + 64 * X3B_WAVES * u;
-      sa[buf][i >> 9][i & 511] = an[u];
+      sa[buf][i / (2 * ROWS)][i % (2 * ROWS)] = an[u];
     }
   };
-  v16f acc[X3B_ZT] = {};
+  v16f acc[ZT] = {};
   X3AdjB<PREC> bc, bn;
   x3_adj_loadb<PREC>(p, g, g_ld, cok, cidx, 0, h, bc);
   fetch_a(0);
@@ -1254,7 +1257,7 @@ __global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(
     const v8u* ah = sa[st & 1][0];
     const v8u* al = sa[st & 1][1];
 #pragma unroll
-    for (int i = 0; i < X3B_ZT; ++i) {
+    for (int i = 0; i < ZT; ++i) {
       const int f = (32 * i + r) * 2 + h;
       acc[i] = mfma16<PREC>(ah[f], bh, acc[i]);
       acc[i] = mfma16<PREC>(al[f], bh, acc[i]);
@@ -1265,7 +1268,7 @@ __global__ __launch_bounds__(64 * X3B_WAVES) __attribute__((amdgpu_waves_per_eu(
   }
   if (!cok) return;
 #pragma unroll
-  for (int i = 0; i < X3B_ZT; ++i)
+  for (int i = 0; i < ZT; ++i)
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int z = zb + 32 * i + 8 * (v >> 2) + 4 * h + (v & 3);
@@ -1550,13 +1553,19 @@ static inline char* wptr(const lamino_plan_s* p, size_t off) {
 // vol rows of v_ld columns.
 static void launch_x3_adj(const KParams& kp, const void* g, int g_ld, float* vol, int v_ld,
                           int vcol0, int ncol, int z0, int nzc, int out_z0, hipStream_t s) {
-  const dim3 grid(cdiv(ncol, 32 * X3B_WAVES), cdiv(nzc, X3B_ROWS));
+  // z chunks of up to 64 slices take blocks of 64 rows (two accumulator
+  // tiles per wave), longer ones blocks of 256
+  const bool narrow = nzc <= 64;
+  const dim3 grid(cdiv(ncol, 32 * X3B_WAVES), cdiv(nzc, narrow ? 64 : 32 * X3B_ZT));
+  const dim3 blk(64 * X3B_WAVES);
+#define X3ADJ(P) (narrow ? k_x3_adj_b<P, 2> : k_x3_adj_b<P, X3B_ZT>)
   if (kp.storage_dtype == LAMINO_F32)
-    hipLaunchKernelGGL(k_x3_adj_b<0>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(X3ADJ(0), grid, blk, 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
   else if (kp.storage_dtype == LAMINO_F16)
-    hipLaunchKernelGGL(k_x3_adj_b<1>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(X3ADJ(1), grid, blk, 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
   else
-    hipLaunchKernelGGL(k_x3_adj_b<2>, grid, dim3(64 * X3B_WAVES), 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+    hipLaunchKernelGGL(X3ADJ(2), grid, blk, 0, s, kp, g, g_ld, vol, v_ld, vcol0, ncol, z0, nzc, out_z0);
+#undef X3ADJ
 }
 
 // Backprojection pipeline.  Device-resident plans with device data and
