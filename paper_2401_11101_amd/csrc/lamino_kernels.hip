@@ -105,6 +105,21 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
 // exchange buffer), writes the spectrum back in natural order, and the
 // block then separates the two real spectra of each pair and writes rows
 // l = 0 .. n_slab-1 of W1, 2 CW consecutive columns per row.
+// Column block and projection of a detector column block.  Neighbouring
+// column blocks read or write the two 64-byte halves of the same 128-byte
+// lines (16 float32 columns each), so each run of 16 dispatched blocks is
+// reordered to place column blocks 2k and 2k + 1 at dispatch positions k
+// and k + 8: hardware workgroup b runs on XCD b mod 8, and both halves of a
+// line then meet in the same XCD's L2.
+__device__ __forceinline__ void det_col_block(int& cb, int& tl) {
+  const int nb = (int)gridDim.x;
+  const int total = nb * (int)gridDim.y;
+  int b = (int)(blockIdx.x + gridDim.x * blockIdx.y);
+  if ((b | 15) < total) b = (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
+  cb = b % nb;
+  tl = b / nb;
+}
+
 constexpr __host__ __device__ int wcol_stride(int R, int cw) { return wfft_xch(R) + 32 / cw; }
 
 template <int R, int CW>
@@ -115,9 +130,10 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
   constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  const int tl = blockIdx.y;
+  int cb, tl;
+  det_col_block(cb, tl);
   const int th = theta0 + tl;
-  const int c0 = blockIdx.x * 2 * CW;
+  const int c0 = cb * 2 * CW;
   float* bf = reinterpret_cast<float*>(buf);
   const size_t row0 = (size_t)(th - data_th0) * p.h;
   const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
@@ -390,9 +406,10 @@ __global__ __launch_bounds__(512) void k_proj_cols_inv_w(KParams p, const float2
   constexpr int S = wcol_stride(R, CW);
   __shared__ float2 buf[CW * S];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
-  const int tl = blockIdx.y;
+  int cb, tl;
+  det_col_block(cb, tl);
   const int th = theta0 + tl;
-  const int c0 = blockIdx.x * 2 * CW;
+  const int c0 = cb * 2 * CW;
   const size_t base = (size_t)tl * p.n_slab * p.w;
   stage_in<float4>(
       p.n_slab * CW,
