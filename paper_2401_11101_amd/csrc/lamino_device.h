@@ -188,10 +188,14 @@ __device__ inline void block_fft(float2* a, int log2N, int B, const float2* __re
 // (i < R / 8), whose 8-point DFTs over m1 and twiddles w64^(m2 l1) give
 // Z[k1][l1][m2]; a second exchange hands lane (k, l1) = (L >> 3, L & 7) the
 // values Z[k1][l1][m2] (m2 = 0..7), and their 8-point DFTs over m2 are
-// X[k1 + R l1 + 8 R l2] (l2 = 0..7).  The exchange buffers hold element
-// (k1, n2) at 72 k1 + n2 and (k1, l1, m2) at 72 k1 + 9 l1 + m2, which
-// spreads every write and read of both exchanges over distinct LDS banks
-// (checked for 16- and 32-lane bank groups of 8-byte values).
+// X[k1 + R l1 + 8 R l2] (l2 = 0..7).  (For R = 16 the second exchange hands
+// lane L the pairs (k1, l1) = (L & 15, (L >> 4) + 4 j) instead, so that
+// each output register holds 64 consecutive entries.)  The exchange buffers
+// hold element (k1, n2) at 72 k1 + n2 and (k1, l1, m2) at 72 k1 + 9 l1 + m2
+// (R = 8) or 65 k1 + 16 l1 + 2 m2 (R = 16); searched over linear layouts,
+// these spread every write and read of both exchanges over distinct LDS
+// banks for R = 8, and leave a few two-way conflicts in the second exchange
+// for R = 16 (checked for 16- and 32-lane bank groups of 8-byte values).
 __host__ __device__ constexpr int wfft_xch(int R) { return 72 * R; }  // exchange buffer (float2)
 
 template <int R>
@@ -242,10 +246,14 @@ __device__ __forceinline__ void dft_reg(float2 v[R], bool inv) {
   }
 }
 
-// Output register q of lane L holds X[wave_out<R>(L, q)].
+// Output register q of lane L holds X[wave_out<R>(L, q)]: for R = 8 lane
+// (k1, l1) = (L >> 3, L & 7) holds X[k1 + 8 l1 + 64 q]; for R = 16 lane
+// (k1, l1) = (L & 15, (L >> 4) + 4 j) holds X[k1 + 16 l1 + 128 l2] in
+// register 8 j + l2, i.e. X[L + 64 j + 128 l2].
 template <int R>
 __device__ __forceinline__ int wave_out(int L, int q) {
-  return (L >> 3) + 8 * (q >> 3) + R * (L & 7) + 8 * R * (q & 7);
+  if constexpr (R == 8) return (L >> 3) + 8 * (L & 7) + 64 * q;
+  return L + 64 * (q >> 3) + 128 * (q & 7);
 }
 
 // In place on v: on entry lane j holds x[j + 64 r] in v[r]; on exit lane L
@@ -272,15 +280,25 @@ __device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<
 #pragma unroll
     for (int k = 1; k < 8; ++k) v[8 * i + k] = cmul(v[8 * i + k], t.b[k - 1]);
   }
+  if constexpr (R == 8) {
 #pragma unroll
-  for (int i = 0; i < R / 8; ++i)
+    for (int k = 0; k < 8; ++k) xch[72 * hi + 9 * k + lo] = v[k];
+    wave_lds_sync();
 #pragma unroll
-    for (int k = 0; k < 8; ++k) xch[72 * (hi + 8 * i) + 9 * k + lo] = v[8 * i + k];
-  wave_lds_sync();
+    for (int m = 0; m < 8; ++m) v[m] = xch[72 * hi + 9 * lo + m];
+  } else {
+    // R = 16: lane L takes (k1, l1) = (L & 15, (L >> 4) + 4 j), so that each
+    // output register covers 64 consecutive entries
 #pragma unroll
-  for (int i = 0; i < R / 8; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int m = 0; m < 8; ++m) v[8 * i + m] = xch[72 * (hi + 8 * i) + 9 * lo + m];
+      for (int k = 0; k < 8; ++k) xch[65 * (hi + 8 * i) + 16 * k + 2 * lo] = v[8 * i + k];
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int m = 0; m < 8; ++m) v[8 * j + m] = xch[65 * (L & 15) + 16 * ((L >> 4) + 4 * j) + 2 * m];
+  }
   wave_lds_sync();
 #pragma unroll
   for (int i = 0; i < R / 8; ++i) r8_compute(0, 0, nullptr, 0, inv, v + 8 * i);
