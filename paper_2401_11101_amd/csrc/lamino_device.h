@@ -204,14 +204,23 @@ struct WaveTw {
   float2 b[7];      // w64^(m2 l1), l1 = 1 .. 7, m2 = lane & 7
 };
 
-template <int R>
+// The lane's twiddles.  With TWL, twa (an LDS table of (R - 1) x 64 values) the
+// first-stage twiddles w^(j k1) are kept there instead of in registers, at
+// twa[(k1 - 1) 64 + lane]: each lane reads only the entries it wrote, so the
+// table needs no barrier, and the waves of a block may share it (they write
+// the same values).
+template <int R, bool TWL = false>
 __device__ __forceinline__ void wave_tw(const float2* __restrict__ tw, int log2max, bool inv,
-                                        WaveTw<R>& t) {
+                                        WaveTw<R>& t, float2* twa = nullptr) {
   constexpr int N = 64 * R;
   constexpr int LOGN = R == 8 ? 9 : 10;
   const int L = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 1; k < R; ++k) t.a[k - 1] = twiddle(tw, ((L * k) & (N - 1)) << (log2max - LOGN), inv);
+  for (int k = 1; k < R; ++k) {
+    const float2 a = twiddle(tw, ((L * k) & (N - 1)) << (log2max - LOGN), inv);
+    if constexpr (TWL) twa[(k - 1) * 64 + L] = a;
+    else t.a[k - 1] = a;
+  }
 #pragma unroll
   for (int k = 1; k < 8; ++k) t.b[k - 1] = twiddle(tw, (((L & 7) * k) & 63) << (log2max - 6), inv);
 }
@@ -258,14 +267,18 @@ __device__ __forceinline__ int wave_out(int L, int q) {
 
 // In place on v: on entry lane j holds x[j + 64 r] in v[r]; on exit lane L
 // holds X[wave_out<R>(L, q)] in v[q].  xch: this wave's wfft_xch(R)-value
-// buffer.
-template <int R>
-__device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<R>& t, bool inv) {
+// buffer; twa: the first-stage twiddle table if wave_tw filled one.
+template <int R, bool TWL = false>
+__device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<R>& t, bool inv,
+                                         const float2* twa = nullptr) {
   const int L = threadIdx.x & 63;
   const int hi = L >> 3, lo = L & 7;
   dft_reg<R>(v, inv);
 #pragma unroll
-  for (int k = 1; k < R; ++k) v[k] = cmul(v[k], t.a[k - 1]);
+  for (int k = 1; k < R; ++k) {
+    if constexpr (TWL) v[k] = cmul(v[k], twa[(k - 1) * 64 + L]);
+    else v[k] = cmul(v[k], t.a[k - 1]);
+  }
 #pragma unroll
   for (int k = 0; k < R; ++k) xch[72 * k + L] = v[k];
   wave_lds_sync();

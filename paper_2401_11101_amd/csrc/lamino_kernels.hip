@@ -235,13 +235,22 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
   __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   float2* xch = xch_all + wv * wfft_xch(R);
+  // 1024-point rows keep the first-stage twiddles in LDS (fewer registers, more waves)
+  __shared__ float2 twa_s[R == 16 ? 15 * 64 : 1];
+  float2* const twa = R == 16 ? twa_s : nullptr;
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   WaveTw<R> t;
-  wave_tw<R>(p.tw, p.log2_twmax, false, t);
-  float f[R];
+  wave_tw<R, R == 16>(p.tw, p.log2_twmax, false, t, twa);
+  // the transfer function at this lane's outputs: registers, or (R = 16)
+  // this lane's own entries of an LDS table
+  __shared__ float f_s[R == 16 ? 16 * 64 : 1];
+  float f[R == 16 ? 1 : R];
 #pragma unroll
-  for (int q = 0; q < R; ++q) f[q] = filt[wave_out<R>(L, q)];
+  for (int q = 0; q < R; ++q) {
+    if constexpr (R == 16) f_s[q * 64 + L] = filt[wave_out<R>(L, q)];
+    else f[q] = filt[wave_out<R>(L, q)];
+  }
   const float2* src = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
@@ -252,11 +261,11 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
       const int c = (L + 64 * r + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p holds column c
       v[r] = c < p.w ? src[(size_t)l * p.w + c] : make_float2(0.f, 0.f);
     }
-    wave_fft<R>(v, xch, t, false);
+    wave_fft<R, R == 16>(v, xch, t, false, twa);
     const size_t o = ((size_t)l * d_nth + (th - d_th0)) * N;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      float2 x = cscale(v[q], f[q]);
+      float2 x = cscale(v[q], R == 16 ? f_s[q * 64 + L] : f[q]);
       if (phase) x = cmul(x, phase[wave_out<R>(L, q)]);
       st_c(D, o + wave_out<R>(L, q), x, p.storage_dtype);
     }
@@ -372,10 +381,13 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, 
   __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   float2* xch = xch_all + wv * wfft_xch(R);
+  // 1024-point rows keep the first-stage twiddles in LDS (fewer registers, more waves)
+  __shared__ float2 twa_s[R == 16 ? 15 * 64 : 1];
+  float2* const twa = R == 16 ? twa_s : nullptr;
   const int tl = blockIdx.y;
   const int th = theta0 + tl;
   WaveTw<R> t;
-  wave_tw<R>(p.tw, p.log2_twmax, true, t);
+  wave_tw<R, R == 16>(p.tw, p.log2_twmax, true, t, twa);
   float2* dst = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
@@ -385,7 +397,7 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, 
 #pragma unroll
     for (int r = 0; r < R; ++r)  // the Nyquist bin (k = 256) is not part of the sum
       v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : ld_c(D, o + L + 64 * r, p.storage_dtype);
-    wave_fft<R>(v, xch, t, true);
+    wave_fft<R, R == 16>(v, xch, t, true, twa);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int c = (wave_out<R>(L, q) + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p -> column c
@@ -906,8 +918,11 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_inv_w(KParams p, 
   __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   float2* xch = xch_all + wv * wfft_xch(R);
+  // 1024-point rows keep the first-stage twiddles in LDS (fewer registers, more waves)
+  __shared__ float2 twa_s[R == 16 ? 15 * 64 : 1];
+  float2* const twa = R == 16 ? twa_s : nullptr;
   WaveTw<R> t;
-  wave_tw<R>(p.tw, p.log2_twmax, true, t);
+  wave_tw<R, R == 16>(p.tw, p.log2_twmax, true, t, twa);
   float2* g = G + (size_t)blockIdx.y * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int r1 = min(r0 + rows_per_wave, N);
@@ -916,7 +931,7 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_inv_w(KParams p, 
     float2 v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = gr[L + 64 * r];
-    wave_fft<R>(v, xch, t, true);
+    wave_fft<R, R == 16>(v, xch, t, true, twa);
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int ix = (wave_out<R>(L, q) + p.n / 2) & (N - 1);  // entry (ix - n/2) mod N -> column ix
@@ -1126,8 +1141,11 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, 
   __shared__ float2 xch_all[WFFT_WAVES * wfft_xch(R)];
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   float2* xch = xch_all + wv * wfft_xch(R);
+  // 1024-point rows keep the first-stage twiddles in LDS (fewer registers, more waves)
+  __shared__ float2 twa_s[R == 16 ? 15 * 64 : 1];
+  float2* const twa = R == 16 ? twa_s : nullptr;
   WaveTw<R> t;
-  wave_tw<R>(p.tw, p.log2_twmax, false, t);
+  wave_tw<R, R == 16>(p.tw, p.log2_twmax, false, t, twa);
   float2* g = G + (size_t)blockIdx.y * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int r1 = min(r0 + rows_per_wave, N);
@@ -1139,7 +1157,7 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, 
       const int ix = (L + 64 * r + p.n / 2) & (N - 1);  // entry (ix - n/2) mod N holds column ix
       v[r] = ix < p.n ? gr[ix] : make_float2(0.f, 0.f);
     }
-    wave_fft<R>(v, xch, t, false);
+    wave_fft<R, R == 16>(v, xch, t, false, twa);
 #pragma unroll
     for (int q = 0; q < R; ++q) gr[wave_out<R>(L, q)] = v[q];
   }
