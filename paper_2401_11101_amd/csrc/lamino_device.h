@@ -6,6 +6,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lamino_common.h"
 #include "lamino_internal.h"
 
@@ -45,12 +47,70 @@ __device__ __forceinline__ void st_r(void* p, size_t i, float v, int dt) {
   else reinterpret_cast<__hip_bfloat16*>(p)[i] = __float2bfloat16(v);
 }
 
+// The same loads with the element type DT fixed at compile time.  With a
+// run-time type each load sits in its own branch and a 16-bit load is
+// converted, after a wait for it, inside that branch, so a run of loads
+// completes one memory latency at a time; hot loops therefore pick the type
+// once (with_storage / with_data) and use these.
+template <int DT>
+__device__ __forceinline__ float2 ld_ct(const void* p, size_t i) {
+  if constexpr (DT == LAMINO_F32) return reinterpret_cast<const float2*>(p)[i];
+  else if constexpr (DT == LAMINO_F16) return __half22float2(reinterpret_cast<const __half2*>(p)[i]);
+  else return __bfloat1622float2(reinterpret_cast<const __hip_bfloat162*>(p)[i]);
+}
+template <int DT>
+__device__ __forceinline__ float ld_rt(const void* p, size_t i) {
+  if constexpr (DT == LAMINO_F32) return reinterpret_cast<const float*>(p)[i];
+  else if constexpr (DT == LAMINO_U8) return (float)reinterpret_cast<const unsigned char*>(p)[i];
+  else if constexpr (DT == LAMINO_U16) return (float)reinterpret_cast<const unsigned short*>(p)[i];
+  else if constexpr (DT == LAMINO_F16) return __half2float(reinterpret_cast<const __half*>(p)[i]);
+  else return __bfloat162float(reinterpret_cast<const __hip_bfloat16*>(p)[i]);
+}
+// A complex element of storage type DT as loaded (float2, or a 32-bit pair
+// of 16-bit values), converted only where it is used, so that a load can
+// stay in flight across other work.
+template <int DT>
+using StoredC = typename std::conditional<DT == LAMINO_F32, float2, unsigned>::type;
+template <int DT>
+__device__ __forceinline__ StoredC<DT> ld_bits(const void* p, size_t i) {
+  return reinterpret_cast<const StoredC<DT>*>(p)[i];
+}
+template <int DT>
+__device__ __forceinline__ float2 bits_c(StoredC<DT> b) {
+  if constexpr (DT == LAMINO_F32) return b;
+  else if constexpr (DT == LAMINO_F16) return __half22float2(__builtin_bit_cast(__half2, b));
+  else return make_float2(__uint_as_float(b << 16), __uint_as_float(b & 0xFFFF0000u));
+}
+template <int DT>
+struct TypeTag {
+  static constexpr int value = DT;
+};
+// f(TypeTag<DT>) for the storage type dt of spectra / slab planes
+template <class F>
+__device__ __forceinline__ void with_storage(int dt, F&& f) {
+  if (dt == LAMINO_F32) f(TypeTag<LAMINO_F32>{});
+  else if (dt == LAMINO_F16) f(TypeTag<LAMINO_F16>{});
+  else f(TypeTag<LAMINO_BF16>{});
+}
+// f(TypeTag<DT>) for the element type dt of detector data
+template <class F>
+__device__ __forceinline__ void with_data(int dt, F&& f) {
+  if (dt == LAMINO_F32) f(TypeTag<LAMINO_F32>{});
+  else if (dt == LAMINO_U8) f(TypeTag<LAMINO_U8>{});
+  else if (dt == LAMINO_U16) f(TypeTag<LAMINO_U16>{});
+  else if (dt == LAMINO_F16) f(TypeTag<LAMINO_F16>{});
+  else f(TypeTag<LAMINO_BF16>{});
+}
+
 // Line integral from raw counts (recording model raw = exp(-d)(flat - dark)
 // + dark): -log of the flat/dark-corrected ratio, clamped below at min_ratio;
 // a pixel with flat <= dark takes min_ratio.
+// (The division runs for every pixel and the result is selected afterwards,
+// so that no branch separates a staging loop's loads from their use.)
 __device__ __forceinline__ float flat_dark_log(float raw, float dark, float flat, float min_ratio) {
   const float den = flat - dark;
-  const float ratio = den > 0.f ? (raw - dark) / den : min_ratio;
+  const float q = (raw - dark) / (den > 0.f ? den : 1.f);
+  const float ratio = den > 0.f ? q : min_ratio;
   return -logf(fmaxf(ratio, min_ratio));
 }
 
@@ -319,17 +379,25 @@ __device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<
 
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places
 // it.  Each thread issues up to FFT_IO fetches before placing any of them,
-// so a block keeps many HBM requests in flight.
+// so a block keeps many HBM requests in flight.  Whole rounds place their
+// values with no bounds test: a test per value lets the compiler sink each
+// fetch into its own branch, where the fetch is waited for at once.  (ld
+// should be branch-free for the same reason: clamp, fetch, then select.)
 template <typename T, typename Ld, typename St>
 __device__ __forceinline__ void stage_in(int total, Ld ld, St st) {
   for (int base = 0; base < total; base += NTF * FFT_IO) {
     T v[FFT_IO];
 #pragma unroll
     for (int u = 0; u < FFT_IO; ++u) v[u] = ld(min(base + u * NTF + (int)threadIdx.x, total - 1));
+    if (base + NTF * FFT_IO <= total) {
 #pragma unroll
-    for (int u = 0; u < FFT_IO; ++u) {
-      const int e = base + u * NTF + (int)threadIdx.x;
-      if (e < total) st(e, v[u]);
+      for (int u = 0; u < FFT_IO; ++u) st(base + u * NTF + (int)threadIdx.x, v[u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < FFT_IO; ++u) {
+        const int e = base + u * NTF + (int)threadIdx.x;
+        if (e < total) st(e, v[u]);
+      }
     }
   }
 }

@@ -49,12 +49,14 @@ __global__ __launch_bounds__(NTF) void k_dir_filter(KParams p, const void* __res
   const int nrows = min(2 * npairs, rows - row0);
   float* bf = reinterpret_cast<float*>(buf);
   const float iw = 1.f / (float)w;
-  stage_in<float>(
-      nrows * w, [&](int e) { return ld_r(data, (size_t)row0 * w + e, p.data_dtype); },
-      [&](int e, float v) {
-        const int rr = div24(e, w, iw), c = e - rr * w;
-        bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
-      });
+  with_data(p.data_dtype, [&](auto ty) {
+    stage_in<float>(
+        nrows * w, [&](int e) { return ld_rt<decltype(ty)::value>(data, (size_t)row0 * w + e); },
+        [&](int e, float v) {
+          const int rr = div24(e, w, iw), c = e - rr * w;
+          bf[2 * ((rr >> 1) * wp + ((c - w / 2) & (wp - 1))) + (rr & 1)] = v;
+        });
+  });
   __syncthreads();
   block_fft<LOGN>(buf, p.log2_wp, npairs, p.tw, p.log2_twmax, false);
   for (int e = threadIdx.x; e < npairs * wp; e += NTF) {

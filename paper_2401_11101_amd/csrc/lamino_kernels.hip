@@ -48,6 +48,16 @@ constexpr int WFFT_CW_WIDE = 8;
 // complex h_p-point FFT along v; the two real spectra are separated by
 // Hermitian symmetry and the half l = 0 .. n_slab-1 is stored.
 // data holds projections data_th0 .. (a whole input or a streamed chunk).
+// f(TypeTag<data type>, TypeTag<raw counts>) for the detector data of a
+// call: raw counts take the dark / flat correction and -log on loading
+template <class F>
+__device__ __forceinline__ void with_data_raw(const KParams& p, F&& f) {
+  with_data(p.data_dtype, [&](auto ty) {
+    if (p.dark) f(ty, TypeTag<1>{});
+    else f(ty, TypeTag<0>{});
+  });
+}
+
 template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __restrict__ data,
                                                       float2* __restrict__ w1, int theta0,
@@ -64,22 +74,24 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
   float* bf = reinterpret_cast<float*>(buf);
   const size_t row0 = (size_t)(th - data_th0) * p.h;
   const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
-  stage_in<float>(
-      p.h * wide,
-      [&](int e) {
-        const int r = div24(e, wide, iwide), c = c0 + e - r * wide;
-        if (c >= p.w) return 0.f;
-        float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
-        if (p.dark) {
-          const size_t q = (size_t)r * p.w + c;
-          v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
-        }
-        return v * fin;
-      },
-      [&](int e, float v) {
-        const int r = div24(e, wide, iwide), cl = e - r * wide;
-        bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
-      });
+  with_data_raw(p, [&](auto ty, auto raw) {
+    stage_in<float>(
+        p.h * wide,
+        [&](int e) {
+          const int r = div24(e, wide, iwide), c = c0 + e - r * wide;
+          const int cs = min(c, p.w - 1);  // past the detector: a valid load, dropped below
+          float v = ld_rt<decltype(ty)::value>(data, (row0 + r) * p.w + cs);
+          if constexpr (decltype(raw)::value) {
+            const size_t q = (size_t)r * p.w + cs;
+            v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
+          }
+          return c < p.w ? v * fin : 0.f;
+        },
+        [&](int e, float v) {
+          const int r = div24(e, wide, iwide), cl = e - r * wide;
+          bf[2 * ((cl >> 1) * hp + ((r - p.h / 2) & (hp - 1))) + (cl & 1)] = v;
+        });
+  });
   __syncthreads();
   block_fft<LOGN>(buf, p.log2_hp, cp, p.tw, p.log2_twmax, false);
   const float2* res = buf;
@@ -137,22 +149,24 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
   float* bf = reinterpret_cast<float*>(buf);
   const size_t row0 = (size_t)(th - data_th0) * p.h;
   const float fin = p.dyn ? p.dyn[0] : 1.f;  // float16 storage: input factor of the call
-  stage_in<float>(
-      p.h * 2 * CW,
-      [&](int e) {
-        const int r = e / (2 * CW), c = c0 + e % (2 * CW);
-        if (c >= p.w) return 0.f;
-        float v = ld_r(data, (row0 + r) * p.w + c, p.data_dtype);
-        if (p.dark) {
-          const size_t q = (size_t)r * p.w + c;
-          v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
-        }
-        return v * fin;
-      },
-      [&](int e, float v) {
-        const int r = e / (2 * CW), cl = e % (2 * CW);
-        bf[2 * ((cl >> 1) * S + ((r - p.h / 2) & (N - 1))) + (cl & 1)] = v;
-      });
+  with_data_raw(p, [&](auto ty, auto raw) {
+    stage_in<float>(
+        p.h * 2 * CW,
+        [&](int e) {
+          const int r = e / (2 * CW), c = c0 + e % (2 * CW);
+          const int cs = min(c, p.w - 1);  // past the detector: a valid load, dropped below
+          float v = ld_rt<decltype(ty)::value>(data, (row0 + r) * p.w + cs);
+          if constexpr (decltype(raw)::value) {
+            const size_t q = (size_t)r * p.w + cs;
+            v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
+          }
+          return c < p.w ? v * fin : 0.f;
+        },
+        [&](int e, float v) {
+          const int r = e / (2 * CW), cl = e % (2 * CW);
+          bf[2 * ((cl >> 1) * S + ((r - p.h / 2) & (N - 1))) + (cl & 1)] = v;
+        });
+  });
   WaveTw<R> t;
   wave_tw<R>(p.tw, p.log2_twmax, false, t);
   __syncthreads();
@@ -294,17 +308,18 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
   const int th = theta0 + tl;
   const int l0 = blockIdx.x * rows;
   const int wp = p.w_p;
-  stage_in<float2>(
-      rows * wp,
-      [&](int e) {
-        const int b = e >> p.log2_wp, k = e & (wp - 1);
-        const int l = l0 + b;
-        float2 v = make_float2(0.f, 0.f);
-        if (l < p.n_slab && k != (wp >> 1))  // the Nyquist bin is not part of the sum
-          v = ld_c(D, ((size_t)l * p.n_theta + th) * wp + k, p.storage_dtype);
-        return v;
-      },
-      [&](int e, float2 v) { buf[e] = v; });
+  with_storage(p.storage_dtype, [&](auto ty) {
+    stage_in<float2>(
+        rows * wp,
+        [&](int e) {
+          const int b = e >> p.log2_wp, k = e & (wp - 1);
+          const int l = l0 + b;
+          const float2 v = ld_ct<decltype(ty)::value>(D, ((size_t)min(l, p.n_slab - 1) * p.n_theta + th) * wp + k);
+          // rows past the last slab drop out; the Nyquist bin is not part of the sum
+          return l < p.n_slab && k != (wp >> 1) ? v : make_float2(0.f, 0.f);
+        },
+        [&](int e, float2 v) { buf[e] = v; });
+  });
   __syncthreads();
   block_fft<LOGN>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, true);
   const float2* res = buf;
@@ -391,19 +406,23 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, 
   float2* dst = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
-  for (int l = l0; l < l1; ++l) {
-    const size_t o = ((size_t)l * p.n_theta + th) * N;
-    float2 v[R];
+  with_storage(p.storage_dtype, [&](auto ty) {
+    for (int l = l0; l < l1; ++l) {
+      const size_t o = ((size_t)l * p.n_theta + th) * N;
+      float2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)  // the Nyquist bin (k = 256) is not part of the sum
-      v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : ld_c(D, o + L + 64 * r, p.storage_dtype);
-    wave_fft<R, R == 16>(v, xch, t, true, twa);
+      for (int r = 0; r < R; ++r) {  // the Nyquist bin (k = N/2) is not part of the sum
+        const float2 x = ld_ct<decltype(ty)::value>(D, o + L + 64 * r);
+        v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : x;
+      }
+      wave_fft<R, R == 16>(v, xch, t, true, twa);
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int c = (wave_out<R>(L, q) + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p -> column c
-      if (c < p.w) dst[(size_t)l * p.w + c] = v[q];
+      for (int q = 0; q < R; ++q) {
+        const int c = (wave_out<R>(L, q) + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p -> column c
+        if (c < p.w) dst[(size_t)l * p.w + c] = v[q];
+      }
     }
-  }
+  });
 }
 
 // k_proj_cols_inv for h_p = N = 64 R (512 or 1024) with one wave per complex column: the half
@@ -569,14 +588,19 @@ __device__ __forceinline__ v16f mfma16(v8u a, v8u b, v16f c) {
 }
 
 // One candidate sample of a lane: position, local tap-0 cell, value.
+// (The value is kept as loaded and converted at staging, so that its load
+// stays in flight during the matrix products of the previous batch.)
+template <int DT>
 struct SpreadCand {
   bool use;
   int lx, ly;
   float X, Y;
-  float2 c;
+  StoredC<DT> c;
 };
 
-// PREC 0: bf16 x3 (float32 storage), 1: float16 x1, 2: bfloat16 x1
+// PREC 0: bf16 x3 (float32 storage), 1: float16 x1, 2: bfloat16 x1; PREC is
+// also the storage type of D
+static_assert(LAMINO_F32 == 0 && LAMINO_F16 == 1 && LAMINO_BF16 == 2, "PREC doubles as the storage type");
 template <int M, int PREC>
 __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict__ D,
                                                float2* __restrict__ G, int slab0, int d_l0, int ns) {
@@ -655,7 +679,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
         const int total = __shfl(incl, 63);
         int jcur = 0;  // interval holding candidate `base`
         // candidate base + lane: interval, position, value
-        auto fetch = [&](int base, SpreadCand& cd) {
+        auto fetch = [&](int base, SpreadCand<PREC>& cd) {
           const int i = base + lane;
           int j = jcur;
           for (int jj = jcur + 1; jj < nseg; ++jj) {
@@ -667,7 +691,7 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
           cd.use = false;
           cd.lx = cd.ly = 0;
           cd.X = cd.Y = 0.f;
-          cd.c = make_float2(0.f, 0.f);
+          cd.c = StoredC<PREC>{};
           const int pj = __shfl(spre, j), mj = __shfl(smlo, j), tj = __shfl(sth, j);
           const float2 cs = make_float2(__shfl(cst.x, j), __shfl(cst.y, j));
           if (i >= total) return;
@@ -677,10 +701,9 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
           cd.ly = (int)floorf(cd.Y) - M + 1 - oy;
           cd.use = cd.lx + W > 0 && cd.lx < SP_T && cd.ly + W > 0 && cd.ly < SP_T;
           if (cd.use)
-            cd.c = ld_c(D, ((size_t)(l - d_l0) * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)),
-                        p.storage_dtype);
+            cd.c = ld_bits<PREC>(D, ((size_t)(l - d_l0) * p.n_theta + tj) * p.w_p + (m & (p.w_p - 1)));
         };
-        SpreadCand cur;
+        SpreadCand<PREC> cur;
         fetch(0, cur);
         for (int base = 0; base < total; base += 64) {
           // stage the candidates whose taps reach the tile
@@ -690,19 +713,20 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
                                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
           if (cur.use) {
             float wx[W], wy[W];
+            const float2 cc = bits_c<PREC>(cur.c);
             gauss_taps<M>(cur.X - floorf(cur.X), p.beta, e2b, wx);
             gauss_taps<M>(cur.Y - floorf(cur.Y), p.beta, e2b, wy);
 #pragma unroll
             for (int k = 0; k < W; ++k) {
               if constexpr (PREC == 0) {
                 st_a[pos * WS + 1 + k] = bf16_split(wy[k]);
-                st_b[pos * WS + 1 + k] = bf16_split2(cur.c.x * wx[k], cur.c.y * wx[k]);
+                st_b[pos * WS + 1 + k] = bf16_split2(cc.x * wx[k], cc.y * wx[k]);
               } else if constexpr (PREC == 1) {
                 st_a[pos * WS + 1 + k] = (unsigned short)f16_bits(wy[k]);
-                st_b[pos * WS + 1 + k] = f16_prod_pair(cur.c.x, cur.c.y, wx[k]);
+                st_b[pos * WS + 1 + k] = f16_prod_pair(cc.x, cc.y, wx[k]);
               } else {
                 st_a[pos * WS + 1 + k] = (unsigned short)bf16_bits(wy[k]);
-                st_b[pos * WS + 1 + k] = bf16_pair(cur.c.x * wx[k], cur.c.y * wx[k]);
+                st_b[pos * WS + 1 + k] = bf16_pair(cc.x * wx[k], cc.y * wx[k]);
               }
             }
             st_l[pos] = (int)(((unsigned)(cur.ly * SA) & 0xFFFFu) | ((unsigned)(cur.lx * SB) << 16));
@@ -1032,18 +1056,21 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
   const int l = slab0 + blockIdx.y;
   lds_zero(buf, cols * N);
   __syncthreads();
-  stage_in<float2>(
-      cols * p.n,
-      [&](int e) {
-        const int y = div24(e, cols, icols), ix = ix0 + e - y * cols;
-        return ix < p.n ? ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype)
-                        : make_float2(0.f, 0.f);
-      },
-      [&](int e, float2 v) {
-        const int y = div24(e, cols, icols), c = e - y * cols;
-        const int ix = ix0 + c;
-        if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, p.deapod[ix] * p.deapod[y]);
-      });
+  with_storage(p.storage_dtype, [&](auto ty) {
+    stage_in<float2>(
+        cols * p.n,
+        [&](int e) {
+          const int y = div24(e, cols, icols), ix = ix0 + e - y * cols;
+          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + min(ix, p.n - 1));
+          return ix < p.n ? v : make_float2(0.f, 0.f);
+        },
+        [&](int e, float2 v) {
+          const int y = div24(e, cols, icols), c = e - y * cols;
+          const int ix = ix0 + c;
+          const float dp = p.deapod[min(ix, p.n - 1)] * p.deapod[y];
+          if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, dp);
+        });
+  });
   __syncthreads();
   block_fft<LOGN>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, false);
   const float2* res = buf;
@@ -1096,17 +1123,21 @@ __global__ __launch_bounds__(512) void k_grid_cols_fwd_w(KParams p, const void* 
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int ix0 = blockIdx.x * CW;
   const int l = slab0 + blockIdx.y;
-  stage_in<float2>(
-      p.n * CW,
-      [&](int e) {
-        const int y = e / CW, ix = ix0 + e % CW;
-        return ix < p.n ? ld_c(g, ((size_t)l * p.n + y) * p.n + ix, p.storage_dtype) : make_float2(0.f, 0.f);
-      },
-      [&](int e, float2 v) {
-        const int y = e / CW, c = e % CW;
-        const int ix = ix0 + c;
-        buf[c * S + ((y - p.n / 2) & (N - 1))] = ix < p.n ? cscale(v, p.deapod[ix] * p.deapod[y]) : v;
-      });
+  with_storage(p.storage_dtype, [&](auto ty) {
+    stage_in<float2>(
+        p.n * CW,
+        [&](int e) {
+          const int y = e / CW, ix = ix0 + e % CW;
+          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + min(ix, p.n - 1));
+          return ix < p.n ? v : make_float2(0.f, 0.f);
+        },
+        [&](int e, float2 v) {
+          const int y = e / CW, c = e % CW;
+          const int ix = ix0 + c;
+          const float dp = p.deapod[min(ix, p.n - 1)] * p.deapod[y];
+          buf[c * S + ((y - p.n / 2) & (N - 1))] = ix < p.n ? cscale(v, dp) : v;
+        });
+  });
   WaveTw<R> t;
   wave_tw<R>(p.tw, p.log2_twmax, false, t);
   __syncthreads();
