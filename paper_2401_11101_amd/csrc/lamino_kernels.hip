@@ -821,10 +821,21 @@ __global__ __launch_bounds__(NT) void k_interp(KParams p, const float2* __restri
   const int half_m = (p.w_p >> 1) - 1;
   const size_t gbase = (size_t)sl * p.grid * p.grid;
   const float iP = 1.f / (float)P;
-  for (int e = threadIdx.x; e < P * P; e += NT) {
-    const int yy = div24(e, P, iP), xx = e - yy * P;
-    const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
-    st[e] = G[gbase + (size_t)ky * p.grid + kx];
+  // FFT_IO loads in flight per thread; a round's surplus lanes repeat the
+  // last cell (same value, same LDS address), so no branch separates a load
+  // from its store
+  for (int e0 = threadIdx.x; e0 < P * P; e0 += NT * FFT_IO) {
+    float2 v[FFT_IO];
+    int ec[FFT_IO];
+#pragma unroll
+    for (int u = 0; u < FFT_IO; ++u) {
+      ec[u] = min(e0 + u * NT, P * P - 1);
+      const int yy = div24(ec[u], P, iP), xx = ec[u] - yy * P;
+      const int ky = (Y0 - M + 1 + yy) & (p.grid - 1), kx = (X0 - M + 1 + xx) & (p.grid - 1);
+      v[u] = G[gbase + (size_t)ky * p.grid + kx];
+    }
+#pragma unroll
+    for (int u = 0; u < FFT_IO; ++u) st[ec[u]] = v[u];
   }
   __syncthreads();
   const float reach = sqrtf(0.25f * (float)p.grid * (float)p.grid + gcl * gcl) + 2.f;
