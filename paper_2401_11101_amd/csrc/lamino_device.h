@@ -59,6 +59,12 @@ __device__ __forceinline__ float2 ld_ct(const void* p, size_t i) {
   else return __bfloat1622float2(reinterpret_cast<const __hip_bfloat162*>(p)[i]);
 }
 template <int DT>
+__device__ __forceinline__ void st_ct(void* p, size_t i, float2 v) {
+  if constexpr (DT == LAMINO_F32) reinterpret_cast<float2*>(p)[i] = v;
+  else if constexpr (DT == LAMINO_F16) reinterpret_cast<__half2*>(p)[i] = __float22half2_rn(v);
+  else reinterpret_cast<__hip_bfloat162*>(p)[i] = __float22bfloat162_rn(v);
+}
+template <int DT>
 __device__ __forceinline__ float ld_rt(const void* p, size_t i) {
   if constexpr (DT == LAMINO_F32) return reinterpret_cast<const float*>(p)[i];
   else if constexpr (DT == LAMINO_U8) return (float)reinterpret_cast<const unsigned char*>(p)[i];
@@ -378,23 +384,23 @@ __device__ __forceinline__ void wave_fft(float2 v[R], float2* xch, const WaveTw<
 }
 
 // Moves `total` elements into LDS: ld(e) fetches element e, st(e, v) places
-// it.  Each thread issues up to FFT_IO fetches before placing any of them,
+// it.  Each thread issues up to IO fetches before placing any of them,
 // so a block keeps many HBM requests in flight.  Whole rounds place their
 // values with no bounds test: a test per value lets the compiler sink each
 // fetch into its own branch, where the fetch is waited for at once.  (ld
 // should be branch-free for the same reason: clamp, fetch, then select.)
-template <typename T, typename Ld, typename St>
+template <typename T, int IO = FFT_IO, typename Ld, typename St>
 __device__ __forceinline__ void stage_in(int total, Ld ld, St st) {
-  for (int base = 0; base < total; base += NTF * FFT_IO) {
-    T v[FFT_IO];
+  for (int base = 0; base < total; base += NTF * IO) {
+    T v[IO];
 #pragma unroll
-    for (int u = 0; u < FFT_IO; ++u) v[u] = ld(min(base + u * NTF + (int)threadIdx.x, total - 1));
-    if (base + NTF * FFT_IO <= total) {
+    for (int u = 0; u < IO; ++u) v[u] = ld(min(base + u * NTF + (int)threadIdx.x, total - 1));
+    if (base + NTF * IO <= total) {
 #pragma unroll
-      for (int u = 0; u < FFT_IO; ++u) st(base + u * NTF + (int)threadIdx.x, v[u]);
+      for (int u = 0; u < IO; ++u) st(base + u * NTF + (int)threadIdx.x, v[u]);
     } else {
 #pragma unroll
-      for (int u = 0; u < FFT_IO; ++u) {
+      for (int u = 0; u < IO; ++u) {
         const int e = base + u * NTF + (int)threadIdx.x;
         if (e < total) st(e, v[u]);
       }

@@ -1023,11 +1023,14 @@ __global__ __launch_bounds__(512) void k_grid_cols_adj_w(KParams p, const float2
   const int wv = threadIdx.x >> 6, L = threadIdx.x & 63;
   const int ix0 = blockIdx.x * CW;
   const float2* gg = G + (size_t)blockIdx.y * N * N;
-  stage_in<float2>(
+  // the block's whole input in one round of loads (2 x 8 per thread at
+  // N = 512, CW = 16)
+  stage_in<float2, N * CW / 512 < 16 ? N * CW / 512 : 16>(
       N * CW,
       [&](int e) {
         const int k2 = e / CW, c = e % CW;
-        return (ix0 + c < p.n) ? gg[(size_t)k2 * N + ix0 + c] : make_float2(0.f, 0.f);
+        const float2 v = gg[(size_t)k2 * N + min(ix0 + c, p.n - 1)];
+        return ix0 + c < p.n ? v : make_float2(0.f, 0.f);
       },
       [&](int e, float2 v) { buf[(e % CW) * S + e / CW] = v; });
   WaveTw<R> t;
@@ -1048,13 +1051,18 @@ __global__ __launch_bounds__(512) void k_grid_cols_adj_w(KParams p, const float2
   }
   __syncthreads();
   const int l = slab0 + blockIdx.y;
-  for (int e = threadIdx.x; e < p.n * CW; e += 512) {
-    const int y = e / CW, c = e % CW;
-    const int ix = ix0 + c;
-    if (ix >= p.n) continue;
-    const float2 v = cscale(buf[c * S + y], p.deapod[ix] * p.deapod[y]);
-    st_c(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix, v, p.storage_dtype);
-  }
+  // each thread keeps one column and takes every (512 / CW)-th row
+  static_assert(512 % CW == 0, "a thread's column must not change between rows");
+  const int c = threadIdx.x % CW, ix = ix0 + c;
+  if (ix >= p.n) return;
+  const float dx = p.deapod[ix];
+  with_storage(p.storage_dtype, [&](auto ty) {
+#pragma unroll 8
+    for (int y = threadIdx.x / CW; y < p.n; y += 512 / CW) {
+      const float2 v = cscale(buf[c * S + y], dx * p.deapod[y]);
+      st_ct<decltype(ty)::value>(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix, v);
+    }
+  });
 }
 
 template <int LOGN>
