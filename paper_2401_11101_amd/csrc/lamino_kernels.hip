@@ -85,7 +85,9 @@ __global__ __launch_bounds__(NTF) void k_proj_cols_fwd(KParams p, const void* __
             const size_t q = (size_t)r * p.w + cs;
             v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
           }
-          return c < p.w ? v * fin : 0.f;
+          // (a factor, not a select: a select of a loaded value lets the compiler move
+          // the load into a branch, where it is waited for at once)
+          return v * (c < p.w ? fin : 0.f);
         },
         [&](int e, float v) {
           const int r = div24(e, wide, iwide), cl = e - r * wide;
@@ -160,7 +162,9 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
             const size_t q = (size_t)r * p.w + cs;
             v = flat_dark_log(v, p.dark[q], p.flat[q], p.min_ratio);
           }
-          return c < p.w ? v * fin : 0.f;
+          // (a factor, not a select: a select of a loaded value lets the compiler move
+          // the load into a branch, where it is waited for at once)
+          return v * (c < p.w ? fin : 0.f);
         },
         [&](int e, float v) {
           const int r = e / (2 * CW), cl = e % (2 * CW);
@@ -314,9 +318,12 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_inv(KParams p, const void* __
         [&](int e) {
           const int b = e >> p.log2_wp, k = e & (wp - 1);
           const int l = l0 + b;
-          const float2 v = ld_ct<decltype(ty)::value>(D, ((size_t)min(l, p.n_slab - 1) * p.n_theta + th) * wp + k);
-          // rows past the last slab drop out; the Nyquist bin is not part of the sum
-          return l < p.n_slab && k != (wp >> 1) ? v : make_float2(0.f, 0.f);
+          // rows past the last slab drop out; the Nyquist bin is not part of the
+          // sum (and may never have been written: its neighbour is read instead);
+          // a factor rather than a select, which would move the load into a branch
+          const int kr = k == (wp >> 1) ? k - 1 : k;
+          const float2 v = ld_ct<decltype(ty)::value>(D, ((size_t)min(l, p.n_slab - 1) * p.n_theta + th) * wp + kr);
+          return cscale(v, l < p.n_slab && k != (wp >> 1) ? 1.f : 0.f);
         },
         [&](int e, float2 v) { buf[e] = v; });
   });
@@ -411,9 +418,13 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_inv_w(KParams p, 
       const size_t o = ((size_t)l * p.n_theta + th) * N;
       float2 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {  // the Nyquist bin (k = N/2) is not part of the sum
-        const float2 x = ld_ct<decltype(ty)::value>(D, o + L + 64 * r);
-        v[r] = (r == R / 2 && L == 0) ? make_float2(0.f, 0.f) : x;
+      for (int r = 0; r < R; ++r) {
+        // the Nyquist bin (k = N/2, lane 0 of r = R/2) is not part of the sum
+        // and may never have been written: that lane reads its neighbour and
+        // drops it
+        const int k = r == R / 2 && L == 0 ? N / 2 - 1 : L + 64 * r;
+        const float2 x = ld_ct<decltype(ty)::value>(D, o + k);
+        v[r] = r == R / 2 && L == 0 ? make_float2(0.f, 0.f) : x;
       }
       wave_fft<R, R == 16>(v, xch, t, true, twa);
 #pragma unroll
@@ -1079,15 +1090,17 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __
     stage_in<float2>(
         cols * p.n,
         [&](int e) {
+          // psi correction with the value's own loads (a select of a loaded
+          // value, or a load at the placing step, would be waited for at once)
           const int y = div24(e, cols, icols), ix = ix0 + e - y * cols;
-          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + min(ix, p.n - 1));
-          return ix < p.n ? v : make_float2(0.f, 0.f);
+          const int ixc = min(ix, p.n - 1);
+          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + ixc);
+          const float dp = p.deapod[ixc] * p.deapod[y];
+          return cscale(v, ix < p.n ? dp : 0.f);
         },
         [&](int e, float2 v) {
           const int y = div24(e, cols, icols), c = e - y * cols;
-          const int ix = ix0 + c;
-          const float dp = p.deapod[min(ix, p.n - 1)] * p.deapod[y];
-          if (ix < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = cscale(v, dp);
+          if (ix0 + c < p.n) buf[c * N + ((y - p.n / 2) & (N - 1))] = v;
         });
   });
   __syncthreads();
@@ -1146,16 +1159,15 @@ __global__ __launch_bounds__(512) void k_grid_cols_fwd_w(KParams p, const void* 
     stage_in<float2>(
         p.n * CW,
         [&](int e) {
+          // psi correction with the value's own loads (a select of a loaded
+          // value, or a load at the placing step, would be waited for at once)
           const int y = e / CW, ix = ix0 + e % CW;
-          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + min(ix, p.n - 1));
-          return ix < p.n ? v : make_float2(0.f, 0.f);
+          const int ixc = min(ix, p.n - 1);
+          const float2 v = ld_ct<decltype(ty)::value>(g, ((size_t)l * p.n + y) * p.n + ixc);
+          const float dp = p.deapod[ixc] * p.deapod[y];
+          return cscale(v, ix < p.n ? dp : 0.f);
         },
-        [&](int e, float2 v) {
-          const int y = e / CW, c = e % CW;
-          const int ix = ix0 + c;
-          const float dp = p.deapod[min(ix, p.n - 1)] * p.deapod[y];
-          buf[c * S + ((y - p.n / 2) & (N - 1))] = ix < p.n ? cscale(v, dp) : v;
-        });
+        [&](int e, float2 v) { buf[(e % CW) * S + (((e / CW) - p.n / 2) & (N - 1))] = v; });
   });
   WaveTw<R> t;
   wave_tw<R>(p.tw, p.log2_twmax, false, t);
