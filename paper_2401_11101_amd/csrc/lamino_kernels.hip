@@ -272,22 +272,24 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
   const float2* src = w1 + (size_t)tl * p.n_slab * p.w;
   const int l0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int l1 = min(l0 + rows_per_wave, p.n_slab);
-  for (int l = l0; l < l1; ++l) {
-    float2 v[R];
+  with_storage(p.storage_dtype, [&](auto ty) {
+    for (int l = l0; l < l1; ++l) {
+      float2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int c = (L + 64 * r + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p holds column c
-      v[r] = c < p.w ? src[(size_t)l * p.w + c] : make_float2(0.f, 0.f);
-    }
-    wave_fft<R, R == 16>(v, xch, t, false, twa);
-    const size_t o = ((size_t)l * d_nth + (th - d_th0)) * N;
+      for (int r = 0; r < R; ++r) {
+        const int c = (L + 64 * r + p.w / 2) & (N - 1);  // entry (c - w/2) mod w_p holds column c
+        v[r] = c < p.w ? src[(size_t)l * p.w + c] : make_float2(0.f, 0.f);
+      }
+      wave_fft<R, R == 16>(v, xch, t, false, twa);
+      const size_t o = ((size_t)l * d_nth + (th - d_th0)) * N;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      float2 x = cscale(v[q], R == 16 ? f_s[q * 64 + L] : f[q]);
-      if (phase) x = cmul(x, phase[wave_out<R>(L, q)]);
-      st_c(D, o + wave_out<R>(L, q), x, p.storage_dtype);
+      for (int q = 0; q < R; ++q) {
+        float2 x = cscale(v[q], R == 16 ? f_s[q * 64 + L] : f[q]);
+        if (phase) x = cmul(x, phase[wave_out<R>(L, q)]);
+        st_ct<decltype(ty)::value>(D, o + wave_out<R>(L, q), x);
+      }
     }
-  }
+  });
 }
 
 // Rotation-axis offset: exp(2 pi i m delta / w_p) for k = m mod w_p, in
