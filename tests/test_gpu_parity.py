@@ -138,6 +138,30 @@ def test_arbitrary_angles():
     assert rel(to_np(plan.fwd(to_dev(f))), nudft.forward(f, g)) < TOL_F32
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("geo", [
+    (10, 20, 9, 14, 18, 2.0),  # block transforms only
+    (4, 200, 7, 150, 200, 2.0),  # 512-point wave transforms (detector and slab)
+    (4, 300, 5, 200, 200, 4.0),  # 1024-point wave transforms
+])
+def test_workspace_contents_do_not_leak(storage, geo):
+    # every kernel reads only what the same call wrote: a workspace filled
+    # with NaN before each call gives the zero-filled workspace's results
+    # bit for bit (a dropped bin that were read and scaled by 0 would turn
+    # NaN, e.g. the Nyquist bin, which the forward path never writes)
+    nz, n, nt, h, w, pad = geo
+    g, plan, f, d = _pair(nz, n, nt, h, w, 30, seed=7, pad_u=pad, pad_v=pad, storage_dtype=storage)
+    D, F = to_dev(d), to_dev(f)
+    for op, x in ((plan.fbp, D), (plan.adj, D), (plan.fwd, F)):
+        out = []
+        for fill in (0, 255):
+            plan.work.fill_(fill)
+            out.append(op(x).clone())
+        torch.cuda.synchronize()
+        assert not torch.isnan(out[1]).any()
+        assert torch.equal(out[0], out[1]), op.__name__
+
+
 def test_repeat_calls_are_stable():
     _, plan, _, d = _pair(16, 24, 16, 16, 24, 30)
     D = to_dev(d)
