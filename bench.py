@@ -713,6 +713,8 @@ def main():
                     help="also time the 1024^2 x 512 volume, CGLS and the TV-regularised ADMM")
     ap.add_argument("--admm", action="store_true",
                     help="also time the TV-regularised ADMM and its kernels (part of --extra)")
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 1024^2 x 512 volume (part of --extra)")
     ap.add_argument("--table1-3072", action="store_true",
                     help="the N = 3072 row of the timing table (fp16, ~2 minutes, 116 GB volume)")
     ap.add_argument("--table1", action="store_true",
@@ -818,9 +820,10 @@ def main():
             log(f"serving from host memory: {args.serve_requests} Poisson requests at 20/s")
             line["serving_host"] = serving(dev, serving_classes(dev, host=True), args.serve_requests,
                                            host=True)
-    if args.extra:
+    if args.extra or args.large:
         log("timing the 1024^2 x 512 volume")
         line["large_volume"] = large_volume(dev, 3)
+    if args.extra:
         log("timing CGLS")
         line["cgls"] = cg_reconstruction(dev)
     if args.extra or args.admm:

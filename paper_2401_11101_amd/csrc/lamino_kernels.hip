@@ -993,7 +993,7 @@ template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* __restrict__ G,
                                                       void* __restrict__ g, int slab0, int cols,
                                                       int g_l0) {
-  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
+  extern __shared__ float2 buf[];  // col_capacity(N) values (launch size)
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float icols = 1.f / (float)cols;
@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(512) void k_grid_cols_adj_w(KParams p, const float2
 template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_grid_cols_fwd(KParams p, const void* __restrict__ g,
                                                       float2* __restrict__ G, int slab0, int cols) {
-  extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
+  extern __shared__ float2 buf[];  // col_capacity(N) values (launch size)
   const int N = p.grid;
   const int ix0 = blockIdx.x * cols;
   const float icols = 1.f / (float)cols;
@@ -1543,6 +1543,12 @@ __global__ __launch_bounds__(256) void k_absmax_final(float* __restrict__ dyn, i
 
 // ================================================================ drivers
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+// Complex values per block of the block slab-column kernels: from 2048
+// points on the block holds the largest buffer (LDS_CPLX_MAX: 4, 2 or 1
+// columns), so that it reads 32-byte rather than 16-byte row segments at 2048
+// points (slab stage of the N = 1024 FBP 40.1 -> 35.9 ms).  The detector
+// column kernels keep fft_capacity (wider blocks were slower there).
+static inline int col_capacity(int N) { return N >= 2048 ? LDS_CPLX_MAX : fft_capacity(N); }
 
 // The instantiation of an FFT kernel for transforms of N points: a fixed
 // size from 256 to 8192 points (8192: the wide passes), else the run-time one.
@@ -1752,6 +1758,7 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
   const size_t lds_h = (size_t)fft_capacity(p->h_p) * sizeof(float2);
   const size_t lds_w = (size_t)fft_capacity(p->w_p) * sizeof(float2);
   const size_t lds_g = (size_t)fft_capacity(p->grid) * sizeof(float2);
+  const size_t lds_gc = (size_t)col_capacity(p->grid) * sizeof(float2);
   for (int t0 = 0, c = 0; t0 < p->n_theta; t0 += p->theta_chunk, ++c) {
     const int nt = std::min(p->theta_chunk, p->n_theta - t0);
     const void* src = d_data;
@@ -1818,7 +1825,7 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
 
   // ---- gridding and slab stages: per slab chunk
   const int rows_g = std::min(fft_capacity(p->grid) / p->grid, p->grid);
-  const int cols_g = std::min(fft_capacity(p->grid) / p->grid, p->n);
+  const int cols_g = std::min(col_capacity(p->grid) / p->grid, p->n);
   for (int s0 = 0, j = 0; s0 < p->n_slab; s0 += p->slab_chunk, ++j) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     const void* Dg = D;
@@ -1863,8 +1870,8 @@ hipError_t run_backprojection(const lamino_plan_s* p, const void* d_data, float*
         hipLaunchKernelGGL((k_grid_cols_adj_w<16, WFFT_CW_WIDE>), dim3(cdiv(p->n, WFFT_CW_WIDE), ns), dim3(512), 0, s, kp,
                            (const float2*)G, gt, s0, g_l0);
       else
-        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
-                           (const float2*)G, gt, s0, cols_g, g_l0);
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_adj, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_gc, s,
+                           kp, (const float2*)G, gt, s0, cols_g, g_l0);
     }
     if (p->spill_g) {
       rec(4 + (j & 1), s);
@@ -1961,10 +1968,11 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
                        dim3(64 * X3B_WAVES), 0, s, kp, d_vol, g);
   }
   const int rows_g = std::min(fft_capacity(p->grid) / p->grid, p->grid);
-  const int cols_g = std::min(fft_capacity(p->grid) / p->grid, p->n);
+  const int cols_g = std::min(col_capacity(p->grid) / p->grid, p->n);
   const size_t lds_h = (size_t)fft_capacity(p->h_p) * sizeof(float2);
   const size_t lds_w = (size_t)fft_capacity(p->w_p) * sizeof(float2);
   const size_t lds_g = (size_t)fft_capacity(p->grid) * sizeof(float2);
+  const size_t lds_gc = (size_t)col_capacity(p->grid) * sizeof(float2);
   for (int s0 = 0; s0 < p->n_slab; s0 += p->slab_chunk) {
     const int ns = std::min(p->slab_chunk, p->n_slab - s0);
     {
@@ -1980,7 +1988,7 @@ hipError_t run_forward(const lamino_plan_s* p, const float* d_vol, void* d_data,
         hipLaunchKernelGGL(k_grid_rows_fwd_w<16>, dim3(1024 / (WFFT_WAVES * WFFT_ROWS), ns), dim3(64 * WFFT_WAVES), 0, s,
                            kp, G, WFFT_ROWS);
       } else {
-        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_g, s, kp,
+        hipLaunchKernelGGL(FFT_KERNEL(k_grid_cols_fwd, p->grid), dim3(cdiv(p->n, cols_g), ns), dim3(NTF), lds_gc, s, kp,
                            (const void*)g, G, s0, cols_g);
         hipLaunchKernelGGL(FFT_KERNEL(k_grid_rows_fwd, p->grid), dim3(cdiv(p->grid, rows_g), ns), dim3(NTF), lds_g, s, kp,
                            G, rows_g);
