@@ -207,7 +207,7 @@ __global__ __launch_bounds__(512) void k_proj_cols_fwd_w(KParams p, const void* 
 // projections per slab (all of them, or one streamed chunk).
 template <int LOGN>
 __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* __restrict__ w1,
-                                                      void* __restrict__ D, const float* filt,
+                                                      void* __restrict__ D, const float* __restrict__ filt,
                                                       const float2* __restrict__ phase, int theta0,
                                                       int rows, int d_nth, int d_th0) {
   extern __shared__ float2 buf[];  // fft_capacity(N) values (launch size)
@@ -229,15 +229,35 @@ __global__ __launch_bounds__(NTF) void k_proj_rows_fwd(KParams p, const float2* 
   __syncthreads();
   block_fft<LOGN>(buf, p.log2_wp, rows, p.tw, p.log2_twmax, false);
   const float2* res = buf;
-  for (int e = threadIdx.x; e < rows * wp; e += NTF) {
-    const int b = e >> p.log2_wp, k = e & (wp - 1);
-    const int l = l0 + b;
-    if (l < p.n_slab) {
-      float2 v = cscale(res[e], filt[k]);
-      if (phase) v = cmul(v, phase[k]);
-      st_c(D, ((size_t)l * d_nth + (th - d_th0)) * wp + k, v, p.storage_dtype);
+  // four elements per thread at a time: their transfer-function (and phase)
+  // loads are issued together, the stores follow
+  const int total = rows * wp;
+  with_storage(p.storage_dtype, [&](auto ty) {
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * NTF) {
+      float2 v[4];
+      if (phase) {  // (a branch per element would wait for each load)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * NTF, total - 1);
+          const int k = e & (wp - 1);
+          v[u] = cmul(cscale(res[e], filt[k]), phase[k]);
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = min(e0 + u * NTF, total - 1);
+          v[u] = cscale(res[e], filt[e & (wp - 1)]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * NTF;
+        const int l = l0 + (e >> p.log2_wp), k = e & (wp - 1);
+        if (e < total && l < p.n_slab)
+          st_ct<decltype(ty)::value>(D, ((size_t)l * d_nth + (th - d_th0)) * wp + k, v[u]);
+      }
     }
-  }
+  });
 }
 
 
@@ -1012,13 +1032,28 @@ __global__ __launch_bounds__(NTF) void k_grid_cols_adj(KParams p, const float2* 
   block_fft<LOGN>(buf, p.log2_grid, cols, p.tw, p.log2_twmax, true);
   const float2* res = buf;
   const int l = slab0 + blockIdx.y;
-  for (int e = threadIdx.x; e < cols * p.n; e += NTF) {
-    const int y = div24(e, cols, icols), c = e - y * cols;
-    const int ix = ix0 + c;
-    if (ix >= p.n) continue;
-    const float2 v = cscale(res[c * N + ((y - p.n / 2) & (N - 1))], p.deapod[ix] * p.deapod[y]);
-    st_c(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix, v, p.storage_dtype);
-  }
+  // four elements per thread at a time: their psi-correction loads are
+  // issued together (unconditionally, clamped), the stores follow
+  const int total = cols * p.n;
+  with_storage(p.storage_dtype, [&](auto ty) {
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * NTF) {
+      float2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * NTF, total - 1);
+        const int y = div24(e, cols, icols), c = e - y * cols;
+        const float dp = p.deapod[min(ix0 + c, p.n - 1)] * p.deapod[y];
+        v[u] = cscale(res[c * N + ((y - p.n / 2) & (N - 1))], dp);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * NTF;
+        const int y = div24(e, cols, icols), c = e - y * cols;
+        if (e < total && ix0 + c < p.n)
+          st_ct<decltype(ty)::value>(g, ((size_t)(l - g_l0) * p.n + y) * p.n + ix0 + c, v[u]);
+      }
+    }
+  });
 }
 
 // k_grid_cols_adj for grid N = 64 R (512 or 1024) with one wave per column: a block stages CW
