@@ -147,7 +147,7 @@ def test_arbitrary_angles():
 def test_workspace_contents_do_not_leak(storage, geo):
     # every kernel reads only what the same call wrote: a workspace filled
     # with NaN before each call gives the zero-filled workspace's results
-    # bit for bit (a dropped bin that were read and scaled by 0 would turn
+    # bit for bit (a dropped bin that was read and scaled by 0 would turn
     # NaN, e.g. the Nyquist bin, which the forward path never writes)
     nz, n, nt, h, w, pad = geo
     g, plan, f, d = _pair(nz, n, nt, h, w, 30, seed=7, pad_u=pad, pad_v=pad, storage_dtype=storage)
