@@ -648,11 +648,25 @@ __global__ __launch_bounds__(64) void k_spread(KParams p, const void* __restrict
   __shared__ TA st_a[64 * WS];
   __shared__ TB st_b[64 * WS];
   const int lane = threadIdx.x;
-  const int sl = (int)(blockIdx.x % (unsigned)ns);  // slabs vary fastest, dense central tiles first
-  const int l = slab0 + sl;
   const int ntx = p.grid / SP_T;
+  // The slabs in two halves, each with its slabs varying fastest and its
+  // dense central tiles first: the second half's grids, written last, are
+  // still in the Infinity Cache when the row pass, which takes the slabs in
+  // reverse order, reads them.
+  const int nh = ns >> 1;
+  const unsigned first = (unsigned)nh * (unsigned)(ntx * ntx);
+  int sl, rank;
+  if (blockIdx.x < first) {
+    sl = (int)(blockIdx.x % (unsigned)nh);
+    rank = (int)(blockIdx.x / (unsigned)nh);
+  } else {
+    const unsigned b2 = blockIdx.x - first;
+    sl = nh + (int)(b2 % (unsigned)(ns - nh));
+    rank = (int)(b2 / (unsigned)(ns - nh));
+  }
+  const int l = slab0 + sl;
   int tx, ty;
-  ring_tile((int)(blockIdx.x / (unsigned)ns), ntx, tx, ty);
+  ring_tile(rank, ntx, tx, ty);
   const int X0 = -(p.grid >> 1) + tx * SP_T;
   const int Y0 = -(p.grid >> 1) + ty * SP_T;
   const float gcl = p.gs * (float)l;
@@ -991,7 +1005,8 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_inv_w(KParams p, 
   float2* const twa = R == 16 ? twa_s : nullptr;
   WaveTw<R> t;
   wave_tw<R, R == 16>(p.tw, p.log2_twmax, true, t, twa);
-  float2* g = G + (size_t)blockIdx.y * N * N;
+  // slabs in reverse order: the gridding wrote the last ones last
+  float2* g = G + (size_t)(gridDim.y - 1 - blockIdx.y) * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int r1 = min(r0 + rows_per_wave, N);
   for (int row = r0; row < r1; ++row) {
