@@ -276,7 +276,9 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_proj_rows_fwd_w(
   // 1024-point rows keep the first-stage twiddles in LDS (fewer registers, more waves)
   __shared__ float2 twa_s[R == 16 ? 15 * 64 : 1];
   float2* const twa = R == 16 ? twa_s : nullptr;
-  const int tl = blockIdx.y;
+  // projections in reverse order: the column pass wrote the last ones last,
+  // and the Infinity Cache still holds them
+  const int tl = (int)gridDim.y - 1 - (int)blockIdx.y;
   const int th = theta0 + tl;
   WaveTw<R> t;
   wave_tw<R, R == 16>(p.tw, p.log2_twmax, false, t, twa);
@@ -1260,7 +1262,8 @@ __global__ __launch_bounds__(64 * WFFT_WAVES) void k_grid_rows_fwd_w(KParams p, 
   float2* const twa = R == 16 ? twa_s : nullptr;
   WaveTw<R> t;
   wave_tw<R, R == 16>(p.tw, p.log2_twmax, false, t, twa);
-  float2* g = G + (size_t)blockIdx.y * N * N;
+  // slabs in reverse order: the column pass wrote the last ones last
+  float2* g = G + (size_t)(gridDim.y - 1 - blockIdx.y) * N * N;
   const int r0 = (blockIdx.x * WFFT_WAVES + wv) * rows_per_wave;
   const int r1 = min(r0 + rows_per_wave, N);
   for (int row = r0; row < r1; ++row) {
